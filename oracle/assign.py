@@ -1,0 +1,88 @@
+"""Adaptive precision assignment (oracle side).
+
+TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
+
+Follows Alg. "Adaptive-precision HODLR Format" and eq. (3.3): with
+nrmAll = ||H||_F^2 and, for each level k, nrm_k the largest squared
+Frobenius norm of a level-k off-diagonal block,
+
+    xi_k = sqrt(nrm_k / nrmAll),   u'_k = eps / (2^(k/2) xi_k),
+    u_k  = the largest u* <= u'_k among {u} and the allowed set,
+
+where u is the working precision (fp64 here) and the level's generators are
+stored in u_k.  Readings where the paper is silent:
+
+* A tie u* == u'_k selects that format (the rule reads "u* <= u'").
+* If no candidate satisfies u* <= u'_k (possible for deep trees), the level
+  falls back to fp64 and ``insufficient[k]`` is set: the bound of Thm. 3.1
+  is then not guaranteed for that level.
+* If xi_k == 0 (every block of the level is zero), u'_k is +inf and the
+  coarsest candidate is taken; nothing is stored for such a level anyway.
+* 2^(k/2) is evaluated as sqrt(2^k) (correctly rounded), and the formula is
+  evaluated left to right in fp64, so that any other implementation doing
+  the same IEEE operations reaches the same decision bit for bit.
+
+``norms_from_factors`` gives the alternative reading in which xi is taken
+from the stored factors (the H~ of Thm. 3.1) instead of the original blocks.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import formats as F
+
+
+@dataclass
+class Assignment:
+    xi: list            # xi_k, k = 1..depth (index k-1)
+    u_prime: list       # u'_k
+    fmt: list           # chosen format name per level
+    insufficient: list  # True where no candidate met u* <= u'_k
+
+
+def level_max_norm2(norm2_blocks, levels) -> list:
+    """nrm_k = max over the level's blocks of ||H_b||_F^2 (k = 1..depth)."""
+    depth = max(levels) if len(levels) else 0
+    out = [0.0] * depth
+    for v, k in zip(norm2_blocks, levels):
+        out[k - 1] = max(out[k - 1], float(v))
+    return out
+
+
+def assign(norm2_all: float, nrm_levels, eps: float, allowed,
+           working: str = "fp64") -> Assignment:
+    """Alg. "Adaptive-precision HODLR Format", the per-level precision choice."""
+    cands = sorted({F.fmt(working).name, *[F.fmt(a).name for a in allowed]},
+                   key=lambda nm: F.FORMATS[nm].u)
+    xis, ups, fmts, bad = [], [], [], []
+    for k, nrm in enumerate(nrm_levels, start=1):
+        xi = math.sqrt(nrm / norm2_all) if norm2_all > 0 else 0.0
+        if xi == 0.0:
+            up = math.inf
+        else:
+            up = eps / (math.sqrt(float(2 ** k)) * xi)
+        ok = [c for c in cands if F.FORMATS[c].u <= up]
+        if ok:
+            choice = max(ok, key=lambda nm: F.FORMATS[nm].u)
+            insufficient = False
+        else:
+            choice = "fp64"
+            insufficient = True
+        xis.append(xi)
+        ups.append(up)
+        fmts.append(choice)
+        bad.append(insufficient)
+    return Assignment(xis, ups, fmts, bad)
+
+
+def norms_from_factors(leaves, U, V):
+    """||H~||_F^2 and ||U_b V_b^T||_F^2 computed from the stored fp64 factors.
+
+    ||U V^T||_F^2 = trace(U^T U V^T V) = sum((U^T U) * (V^T V)).
+    """
+    nb = np.array([float(np.sum((u.T @ u) * (v.T @ v))) for u, v in zip(U, V)])
+    total = float(sum(float(np.sum(d * d)) for d in leaves) + nb.sum())
+    return total, nb
