@@ -1,0 +1,213 @@
+/*
+ * hodlr.h -- C ABI of the MI355X (gfx950) mixed-precision HODLR
+ * matrix-(multi)vector product.
+ *
+ * Method: Carson, Chen, Liu, "Mixed Precision HODLR Matrices"
+ * (arXiv 2407.21637).  The library holds an eps-HODLR operator given as
+ * fp64 leaf blocks and truncated-SVD factors U_b V_b^T of every off-diagonal
+ * block, stores each level's factors in the precision the adaptive rule
+ * picks (Alg. "Adaptive-precision HODLR Format", eq. (3.3)) or that the
+ * caller forces (Alg. "Mixed-precision HODLR Format"), and computes
+ * Y = A_H X on the GPU (Alg. "HODLR_MATVEC").
+ *
+ * Conventions shared by every entry point:
+ *  - All functions return hodlr_status; no exception or abort crosses the
+ *    ABI.  On error nothing is enqueued on any stream and the handle is
+ *    unchanged; hodlr_last_error() gives a detail string (thread-local).
+ *  - Matrices are column-major.  X and Y are n x nrhs with leading
+ *    dimension ldx, ldy >= n; Y is overwritten (the algorithm starts from
+ *    b = 0).  X and Y are device pointers owned by the caller and must stay
+ *    valid until the stream work completes.
+ *  - Host input arrays passed to hodlr_create are deep-copied; the caller
+ *    may free them when the call returns.  Device memory of an operator is
+ *    owned by the library and released by hodlr_destroy.
+ *  - Indices are 0-based.  Node j of level k (j = 0..2^k-1) is the paper's
+ *    I_{j+1}^k (Def. 2.1).  The canonical order of the 2^(depth+1)-2
+ *    off-diagonal blocks is: level k ascending, then row node j ascending;
+ *    block (k, j) has rows node j and columns node j^1 (its sibling), so the
+ *    upper block of each pair (rows I_{2i-1}, cols I_{2i}, eq. (2.1))
+ *    precedes the lower one, and its index is (2^k - 2) + j.
+ *  - Threading: after create/assign, a handle is read-only, and matvec
+ *    calls on the same handle may run concurrently on different streams
+ *    (each call uses its own workspace slot; see hodlr_matvec).  create,
+ *    assign, set_level_precisions and destroy must not overlap other use of
+ *    the same handle.
+ */
+#ifndef HODLR_H
+#define HODLR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hodlr_op_s* hodlr_op;
+
+typedef enum {
+    HODLR_OK = 0,
+    HODLR_E_ARG = 1,          /* invalid or inconsistent argument */
+    HODLR_E_STATE = 2,        /* wrong state (e.g. host-only handle asked for a product) */
+    HODLR_E_NOMEM = 3,        /* host or device allocation failed */
+    HODLR_E_DEVICE = 4,       /* a HIP runtime call or a launch failed */
+    HODLR_E_RANGE = 5,        /* a factor overflows its storage format (no column scaling) */
+    HODLR_E_UNSUPPORTED = 6   /* valid request this build does not support */
+} hodlr_status;
+
+/* Storage / arithmetic formats.  u = 2^-t: fp64 2^-53, fp32 2^-24, bf16 2^-8,
+ * fp16 2^-11, fp8 e4m3 (OCP E4M3FN, max 448) 2^-4, fp8 e5m2 (the paper's q52)
+ * 2^-3 (Table 1.1). */
+typedef enum {
+    HODLR_FP64 = 0,
+    HODLR_FP32 = 1,
+    HODLR_BF16 = 2,
+    HODLR_FP16 = 3,
+    HODLR_FP8_E4M3 = 4,
+    HODLR_FP8_E5M2 = 5
+} hodlr_dtype;
+
+/* Flags of hodlr_assign_precision / hodlr_set_level_precisions. */
+#define HODLR_NO_COLUMN_SCALE 0x1u  /* store fp16/fp8 without per-column 2^e scales */
+#define HODLR_ACC_FP32        0x2u  /* force fp32 accumulation of Y */
+#define HODLR_ACC_FP64        0x4u  /* force fp64 accumulation of Y */
+
+/* One off-diagonal block U V^T: U is r_b x rank (orthonormal columns,
+ * eq. (3.1)), V is c_b x rank, both fp64 column-major on the host. */
+typedef struct {
+    int32_t rank;
+    const double* U;
+    int64_t ldu;
+    const double* V;
+    int64_t ldv;
+} hodlr_lowrank;
+
+typedef struct {
+    int64_t n;
+    int32_t depth;
+    int32_t nblocks;          /* 2^(depth+1) - 2 */
+    int32_t acc_dtype;        /* HODLR_FP32 or HODLR_FP64: accumulation of Y */
+    int32_t max_rank;
+    int32_t on_device;        /* 1 if the operator lives on a GPU */
+    int32_t device;
+    double eps;               /* eps of the last assign (0 after create / set_level) */
+    int64_t leaf_bytes;       /* fp64 leaf blocks as stored (8 sum m_i^2) */
+    int64_t factor_bytes;     /* sum_b (r_b + c_b) p_b s(f_b): codes of all U, V */
+    int64_t scale_bytes;      /* one byte per scaled column */
+    int64_t device_bytes;     /* size of the packed device image incl. padding */
+} hodlr_info;
+
+typedef struct {
+    int32_t level;            /* k = 1..depth */
+    int32_t rank;             /* p_b */
+    int64_t row0, nrows;      /* rows of the block: node j of level k */
+    int64_t col0, ncols;      /* columns: node j^1 */
+    int32_t dtype;            /* storage format of the block's level */
+    int32_t scaled;           /* 1 if per-column exponents are in use */
+} hodlr_block_info;
+
+/* ---- tree (Def. 2.1; left child = ceil(parent/2), Sect. 4) ------------ */
+
+/* Smallest depth l >= 0 with leaf * 2^l >= n (leaves of the ceil split then
+ * hold at most `leaf` indices).  Returns -1 if n < 1 or leaf < 1. */
+int32_t hodlr_depth_for_leaf(int64_t n, int64_t leaf);
+
+/* Node boundaries of every level.  leaf_bounds: NULL for the ceil split, or
+ * 2^depth+1 non-decreasing values from 0 to n (empty nodes allowed).
+ * bounds_out receives levels 0..depth one after another, level k holding
+ * 2^k+1 values; total 2^(depth+1) + depth values.  E_ARG on bad input. */
+hodlr_status hodlr_tree_bounds(int64_t n, int32_t depth, const int64_t* leaf_bounds,
+                               int64_t* bounds_out);
+
+/* Canonical off-diagonal blocks (eq. (2.1)): 5 int64 per block
+ * (level, row0, nrows, col0, ncols), 2^(depth+1)-2 blocks. */
+hodlr_status hodlr_tree_blocks(int64_t n, int32_t depth, const int64_t* leaf_bounds,
+                               int64_t* desc_out);
+
+/* ---- operator ------------------------------------------------------- */
+
+/* Create an operator from fp64 leaves (2^depth blocks, leaf i is m_i x m_i
+ * column-major with leading dimension ld_leaves[i] >= m_i) and the
+ * 2^(depth+1)-2 off-diagonal blocks in canonical order (rank <= min(r_b,
+ * c_b); rank 0 allowed).  depth >= 0, n >= 1.  device >= 0 uploads the
+ * operator to that GPU; device = -1 builds a host-only handle (tree, rule,
+ * packing and export work; products return E_STATE).  The new operator is
+ * uniform fp64 (every u_k = fp64) with fp64 accumulation, i.e. the
+ * same-GPU uniform-precision baseline. */
+hodlr_status hodlr_create(hodlr_op* out, int64_t n, int32_t depth, const int64_t* leaf_bounds,
+                          const double* const* leaves, const int64_t* ld_leaves,
+                          const hodlr_lowrank* blocks, int32_t device);
+
+/* Adaptive precision (Alg. "Adaptive-precision HODLR Format", eq. (3.3)):
+ * for each level k, xi_k = sqrt(nrm_k / nrmAll), u'_k = eps / (2^(k/2) xi_k)
+ * (2^(k/2) evaluated as sqrt(2^k)), and u_k is the largest unit roundoff
+ * <= u'_k among fp64 and `allowed` (n_allowed entries of hodlr_dtype).
+ * norms2: NULL, or 1 + nblocks values: ||A||_F^2 followed by ||A_b||_F^2 of
+ * the original blocks in canonical order (nrm_k is their maximum over level
+ * k).  With NULL the norms are computed from the stored fp64 factors and
+ * leaves (the H~ of Thm. 3.1).  If no format meets u'_k the level is fp64
+ * and marked insufficient; if xi_k = 0 the coarsest allowed format is used.
+ * Accumulation: fp64 if eps < 1e-7, else fp32, unless a HODLR_ACC_* flag
+ * forces it.  The factors are then quantised (round to nearest even, once,
+ * from fp64; fp16/fp8 columns scaled by 2^e_j, e_j the largest integer with
+ * max_i |F_ij| 2^e_j <= the format's largest finite value) and repacked.
+ * E_RANGE if HODLR_NO_COLUMN_SCALE is set and a value overflows. */
+hodlr_status hodlr_assign_precision(hodlr_op op, double eps, const int32_t* allowed,
+                                    int32_t n_allowed, const double* norms2, uint32_t flags);
+
+/* Explicit per-level formats (Alg. "Mixed-precision HODLR Format"):
+ * per_level[k-1] is level k's storage format.  Accumulation: fp64 when
+ * every level is fp64, else fp32, unless a HODLR_ACC_* flag forces it. */
+hodlr_status hodlr_set_level_precisions(hodlr_op op, const int32_t* per_level, uint32_t flags);
+
+/* The last assignment of level k (1..depth): format, xi_k, u'_k and the
+ * insufficient mark (xi and u' are 0 after create / set_level). */
+hodlr_status hodlr_get_level(hodlr_op op, int32_t level, int32_t* dtype, double* xi,
+                             double* u_prime, int32_t* insufficient);
+
+hodlr_status hodlr_get_info(hodlr_op op, hodlr_info* info);
+hodlr_status hodlr_get_block(hodlr_op op, int32_t block, hodlr_block_info* info);
+
+/* Stored codes of block b: u_codes gets r_b x rank codes (column-major,
+ * ld = r_b, element size s(f) bytes: the format's bit patterns), u_exp the
+ * rank column exponents e_j (value = decode(code) * 2^-e_j; all 0 when
+ * unscaled); v_codes / v_exp likewise for V (c_b x rank).  Any pointer may
+ * be NULL.  from_device = 1 reads the uploaded image back from the GPU
+ * (device handles only); 0 re-derives it on the host with the same packer. */
+hodlr_status hodlr_export_block(hodlr_op op, int32_t block, void* u_codes, int8_t* u_exp,
+                                void* v_codes, int8_t* v_exp, int32_t from_device);
+
+/* Y = A_H X (Alg. "HODLR_MATVEC").  xy_dtype is HODLR_FP32 or HODLR_FP64
+ * for both X and Y.  Leaf products D_i X_i run in fp64; a level stored in
+ * fp64 runs in fp64; other levels run in the accumulation precision, with
+ * the stored codes converted in registers.  stream is a hipStream_t (NULL:
+ * the default stream).  The call only enqueues work; on first use with a
+ * larger nrhs it may allocate (and synchronise for) a bigger workspace. */
+hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                          int32_t nrhs, int32_t xy_dtype, void* stream);
+
+/* count independent products Y_i = A_i X_i in one persistent launch.
+ * Operators may differ in everything but must live on the same device.
+ * Arrays of length count. */
+hodlr_status hodlr_matvec_batched(const hodlr_op* ops, int32_t count, const void* const* X,
+                                  const int64_t* ldx, void* const* Y, const int64_t* ldy,
+                                  const int32_t* nrhs, const int32_t* xy_dtype, void* stream);
+
+/* Per-phase GPU timing.  capacity > 0 makes the next `capacity` products
+ * of this handle record a HIP event pair around each of their kernel phases
+ * on the launch stream (0 turns recording off and drops the records).
+ * Phases: 0 padded copy of X, 1 contraction, 2 reduction of T,
+ * 3 expansion + leaves.  hodlr_profile_read synchronises on the recorded
+ * events and returns, per phase, the summed duration in milliseconds and
+ * the number of launches timed; it then clears the records. */
+hodlr_status hodlr_profile(hodlr_op op, int32_t capacity);
+hodlr_status hodlr_profile_read(hodlr_op op, double* ms_per_phase, int64_t* launches_per_phase);
+
+hodlr_status hodlr_destroy(hodlr_op op);
+
+const char* hodlr_status_string(hodlr_status s);
+const char* hodlr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HODLR_H */

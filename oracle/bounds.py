@@ -17,6 +17,11 @@ TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
   (gamma_n = n u / (1 - n u)): a chain of at most M rounded operations per
   output entry gives |y^ - y| <= gamma_M(u_acc) z + u_out |y| + gamma_M(2^-53) z
   with z = |H^| |x| (``matvec.matvec_abs``).
+* ``tolerance_prob``: the same chain under the probabilistic model of
+  rounding errors (independent, mean-zero relative errors; Higham and Mary,
+  SIAM J. Sci. Comput. 41 (2019)): |y^ - y| <= lambda sqrt(M) u_acc z +
+  u_out |y| + gamma_M(2^-53) z with probability at least 1 - delta for each
+  of N entries when lambda = sqrt(2 log(2 M N / delta)); delta = 1e-6.
 """
 from __future__ import annotations
 
@@ -70,3 +75,11 @@ def tolerance(z: np.ndarray, y_ref: np.ndarray, M: int, u_acc: float,
               u_out: float) -> np.ndarray:
     """Componentwise acceptance bound (see module docstring)."""
     return gamma(M, u_acc) * z + u_out * np.abs(y_ref) + gamma(M, 2.0 ** -53) * z
+
+
+def tolerance_prob(z: np.ndarray, y_ref: np.ndarray, M: int, u_acc: float, u_out: float,
+                   delta: float = 1e-6) -> np.ndarray:
+    """Probabilistic componentwise bound (see module docstring)."""
+    N = max(1, int(np.size(z)))
+    lam = math.sqrt(2.0 * math.log(2.0 * M * N / delta))
+    return lam * math.sqrt(M) * u_acc * z + u_out * np.abs(y_ref) + gamma(M, 2.0 ** -53) * z

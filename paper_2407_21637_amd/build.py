@@ -1,0 +1,63 @@
+"""Build the HIP library ``libhodlr.so`` for gfx950 in-tree.
+
+    python -m paper_2407_21637_amd.build        (or build() from Python)
+
+Compiles ``csrc/host.cpp`` (host core and C ABI) and ``csrc/kernels.hip``
+(device kernels) with hipcc and links them into
+``paper_2407_21637_amd/libhodlr.so``.  Packed-fp32 instructions are turned
+off for the device code (``-packed-fp32-ops``).
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libhodlr.so")
+ARCH = os.environ.get("HODLR_OFFLOAD_ARCH", "gfx950")
+
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _hipcc():
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(" ".join(cmd) + "\n" + r.stdout)
+        raise RuntimeError(f"build step failed: {cmd[-1]}")
+    return r.stdout
+
+
+def build(verbose: bool = False) -> str:
+    hipcc = _hipcc()
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    with tempfile.TemporaryDirectory(prefix="hodlr_build_") as tmp:
+        host_o = os.path.join(tmp, "host.o")
+        kern_o = os.path.join(tmp, "kernels.o")
+        _run([hipcc, "-std=c++17", "-O2", "-fPIC", "-Wall", "-c", *inc,
+              os.path.join(CSRC, "host.cpp"), "-o", host_o])
+        _run([hipcc, "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-c", *inc,
+              "-x", "hip", os.path.join(CSRC, "kernels.hip"), "-o", kern_o])
+        tmp_lib = os.path.join(tmp, "libhodlr.so")
+        _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", host_o, kern_o, "-o", tmp_lib,
+              "-lpthread"])
+        shutil.copyfile(tmp_lib, LIB + ".tmp")
+        os.replace(LIB + ".tmp", LIB)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

@@ -1,0 +1,111 @@
+// Internal layout shared by the host core (host.cpp) and the HIP kernels
+// (kernels.hip).  Not part of the public ABI.
+//
+// Device image of one operator
+// ----------------------------
+// Rows are addressed in a padded row space: leaf i occupies padded rows
+// [lprow0_i, lprow0_i + mp_i) with mp_i = m_i rounded up to kRowAlign, and
+// a node of any level is the concatenation of its leaves, so every node is
+// one contiguous padded range.  Padding rows hold zeros in every factor
+// panel and in the leaf blocks.
+//
+//  * leaves: fp64, leaf i column-major mp_i x mp_i at element offset d_off.
+//  * factor panels: for block b (rows = node j of level k, columns = node
+//    j^1), the U panel covers the padded rows of node j and the V panel the
+//    padded rows of node j^1; both column-major with ld = padded node rows,
+//    rank_b columns, codes of the level's format, 256-byte aligned.
+//  * tscale_b[j] = 2^-(eV_j + eU_j) times the decode compensation of the
+//    format (fp8 e4m3 decodes through fp16 at 2^-8 of its value, once per
+//    factor), applied once to T_b = V_b^T X.
+//  * contraction work items split the V panel rows of each block into
+//    chunks; partial results land in a workspace and are summed per block
+//    in a fixed order (deterministic).
+#pragma once
+
+#include <cstdint>
+
+namespace hodlr {
+
+enum Fmt : int32_t { F64 = 0, F32 = 1, BF16 = 2, F16 = 3, E4M3 = 4, E5M2 = 5, NFMT = 6 };
+
+constexpr int kRowAlign = 16;        // padded rows per leaf are a multiple of this
+constexpr int kPanelAlign = 256;     // byte alignment of every panel
+
+inline int fmt_bytes(int f) {
+    return f == F64 ? 8 : f == F32 ? 4 : (f == BF16 || f == F16) ? 2 : 1;
+}
+
+struct BlockDesc {        // one per off-diagonal block, canonical order
+    int64_t u_off;        // byte offset of the U panel in the factor buffer
+    int64_t v_off;        // byte offset of the V panel
+    int64_t ts_off;       // offset of tscale (rank doubles)
+    int64_t t_off;        // offset of T_b in units of rank (x nrhs doubles)
+    int32_t rank;
+    int32_t fmt;
+    int32_t level;
+    int32_t urow0;        // padded row start of the row node (U panel rows)
+    int32_t urows;        // padded rows of the row node (= U panel ld)
+    int32_t vrow0;        // padded row start of the column node
+    int32_t vrows;        // padded rows of the column node (= V panel ld)
+    int32_t item0;        // first contraction item of this block
+    int32_t nitems;       // number of contraction items
+    int32_t pad_;
+};
+
+struct LeafDesc {
+    int64_t d_off;        // element offset of D_i (doubles)
+    int64_t row0;         // first (unpadded) row of the leaf
+    int32_t m;            // real rows
+    int32_t mp;           // padded rows (= ld of D_i)
+    int32_t prow0;        // padded row start
+    int32_t pad_;
+};
+
+struct CItem {            // contraction work item: rows [r0, r0+nr) of a V panel
+    int32_t block;
+    int32_t r0;
+    int32_t nr;
+    int32_t pad_;
+    int64_t poff;         // partial offset in units of rank (x nrhs doubles)
+};
+
+struct ETile {            // expansion + leaf tile: padded rows [r0, r0+nr) of leaf
+    int32_t leaf;
+    int32_t r0;
+    int32_t nr;
+    int32_t pad_;
+};
+
+// Everything a launch needs, by value.
+struct KParams {
+    const uint8_t* fac;          // factor panels
+    const double* leafd;         // leaf blocks
+    const BlockDesc* blocks;
+    const LeafDesc* leaves;
+    const CItem* citems;
+    const ETile* etiles;
+    const double* tscale;
+    double* partial;             // workspace: sum over items of rank * nrhs
+    double* T;                   // workspace: sum over blocks of rank * nrhs
+    void* xpad;                  // workspace: padded copy of X (npad * nrhs), if needed
+    int64_t npad;                // padded rows
+    int32_t depth;
+    int32_t nblocks;
+    int32_t nleaves;
+    int32_t ncitems;
+    int32_t netiles;
+    int32_t padded;              // 1 if any leaf has padding rows (X goes through xpad)
+};
+
+constexpr int kPhases = 4;     // padded X copy, contraction, reduction, expansion
+
+// Launch the whole product on `stream`.  xy_double: X/Y are fp64 (else fp32);
+// acc_double: accumulation precision of Y.  events: NULL, or 2 * kPhases
+// hipEvent_t recorded before/after each phase that runs (a phase that does
+// not run leaves its pair unrecorded; `ran` reports which did).
+// Returns a hipError_t as int.
+int launch_matvec(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                  int nrhs, bool xy_double, bool acc_double, void* stream, void* const* events,
+                  bool* ran);
+
+}  // namespace hodlr

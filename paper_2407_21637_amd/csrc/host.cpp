@@ -1,0 +1,1103 @@
+// Host core of the HODLR library: cluster tree, storage-format codecs,
+// adaptive precision assignment, packing of the device image and the C ABI.
+//
+// Method: Carson, Chen, Liu, "Mixed Precision HODLR Matrices"
+// (arXiv 2407.21637).  Section references are to that paper.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cfloat>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/hodlr.h"
+#include "hodlr_internal.h"
+
+using namespace hodlr;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+namespace {
+thread_local std::string g_last_error;
+
+hodlr_status fail(hodlr_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+hodlr_status ok() {
+    g_last_error.clear();
+    return HODLR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// formats (Table 1.1, plus OCP fp8 E4M3FN)
+// ---------------------------------------------------------------------------
+struct FmtInfo {
+    int t;          // significand bits incl. the implicit one; u = 2^-t
+    int emin, emax;
+    int ebits, bias;
+    double maxf;    // largest finite value
+};
+
+const FmtInfo kFmt[NFMT] = {
+    {53, -1022, 1023, 11, 1023, DBL_MAX},
+    {24, -126, 127, 8, 127, FLT_MAX},
+    {8, -126, 127, 8, 127, 0x1.fep127},
+    {11, -14, 15, 5, 15, 65504.0},
+    {4, -6, 8, 4, 7, 448.0},
+    {3, -14, 15, 5, 15, 57344.0},
+};
+
+double unit_roundoff(int f) { return std::ldexp(1.0, -kFmt[f].t); }
+
+bool scaled_format(int f) { return f == F16 || f == E4M3 || f == E5M2; }
+
+// Round x (fp64) to format f with round-to-nearest-even, once, and return
+// the bit pattern.  Works on the fp64 bit fields: the exact significand is
+// shifted right to the target quantum 2^(max(lead, emin) - t + 1) (gradual
+// underflow below 2^emin) with the discarded bits deciding the rounding.
+// *overflow is set when the rounded value exceeds the largest finite value
+// (or x is not finite).
+uint64_t encode_rne(double x, int f, bool* overflow) {
+    uint64_t bits;
+    std::memcpy(&bits, &x, 8);
+    if (f == F64) return bits;
+    const FmtInfo& F = kFmt[f];
+    const int nbits = 8 * fmt_bytes(f);
+    const int mbits = F.t - 1;
+    const uint64_t sgn = (bits >> 63) << (nbits - 1);
+    const int E = int((bits >> 52) & 0x7ff);
+    const uint64_t M = bits & ((uint64_t(1) << 52) - 1);
+    if (E == 0x7ff) {
+        *overflow = true;
+        return sgn | (((uint64_t(1) << F.ebits) - 1) << mbits);
+    }
+    if (E == 0 && M == 0) return sgn;
+    uint64_t sig;
+    int e2, lead;
+    if (E) {
+        sig = M | (uint64_t(1) << 52);
+        e2 = E - 1075;
+        lead = E - 1023;
+    } else {
+        sig = M;
+        e2 = -1074;
+        lead = -1074 + (63 - __builtin_clzll(M));
+    }
+    int q = std::max(lead, F.emin) - mbits;
+    const int shift = q - e2;  // >= 0: every target is narrower than fp64
+    uint64_t r;
+    if (shift >= 64) {
+        r = 0;
+    } else if (shift == 0) {
+        r = sig;
+    } else {
+        r = sig >> shift;
+        const uint64_t rem = sig & ((uint64_t(1) << shift) - 1);
+        const uint64_t half = uint64_t(1) << (shift - 1);
+        if (rem > half || (rem == half && (r & 1))) ++r;
+    }
+    if (r == 0) return sgn;
+    const uint64_t hidden = uint64_t(1) << mbits;
+    if (r >= hidden) {
+        if (r == (hidden << 1)) {
+            r >>= 1;
+            ++q;
+        }
+        if (std::ldexp(double(r), q) > F.maxf) {
+            *overflow = true;
+            return sgn | (((uint64_t(1) << F.ebits) - 1) << mbits);
+        }
+        const uint64_t expf = uint64_t(q + mbits + F.bias);
+        return sgn | (expf << mbits) | (r - hidden);
+    }
+    return sgn | r;  // subnormal: exponent field 0
+}
+
+// Largest integer e with amax * 2^e <= maxf (0 for amax == 0), from the
+// binary exponents: amax = ma 2^ea, maxf = mf 2^ef with ma, mf in [0.5, 1).
+int column_exponent(int f, double amax) {
+    if (amax == 0.0) return 0;
+    int ea, ef;
+    const double ma = std::frexp(amax, &ea);
+    const double mf = std::frexp(kFmt[f].maxf, &ef);
+    return ef - ea - (ma > mf ? 1 : 0);
+}
+
+template <typename Fn>
+void parallel_for(int64_t n, Fn fn) {
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 2 || nt == 1) {
+        for (int64_t i = 0; i < n; ++i) fn(i);
+        return;
+    }
+    std::atomic<int64_t> next(0);
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&]() {
+            for (int64_t i; (i = next.fetch_add(1)) < n;) fn(i);
+        });
+    for (auto& x : th) x.join();
+}
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// tree (Def. 2.1; left child = ceil(parent / 2) as in Sect. 4)
+// ---------------------------------------------------------------------------
+// Fills all levels 0..depth, level k at offset (2^k - 1) + k with 2^k + 1
+// values.  Returns false on inconsistent leaf bounds.
+bool build_bounds(int64_t n, int depth, const int64_t* leaf_bounds, std::vector<int64_t>& out) {
+    out.assign((size_t(1) << (depth + 1)) + depth, 0);
+    auto lvl = [&](int k) { return out.data() + ((int64_t(1) << k) - 1) + k; };
+    if (!leaf_bounds) {
+        int64_t* l0 = lvl(0);
+        l0[0] = 0;
+        l0[1] = n;
+        for (int k = 0; k < depth; ++k) {
+            const int64_t* p = lvl(k);
+            int64_t* c = lvl(k + 1);
+            c[0] = 0;
+            for (int64_t j = 0; j < (int64_t(1) << k); ++j) {
+                const int64_t a = p[j], b = p[j + 1];
+                c[2 * j + 1] = a + (b - a + 1) / 2;
+                c[2 * j + 2] = b;
+            }
+        }
+        return true;
+    }
+    const int64_t nl = int64_t(1) << depth;
+    if (leaf_bounds[0] != 0 || leaf_bounds[nl] != n) return false;
+    for (int64_t i = 0; i < nl; ++i)
+        if (leaf_bounds[i] > leaf_bounds[i + 1]) return false;
+    for (int k = 0; k <= depth; ++k) {
+        const int64_t step = int64_t(1) << (depth - k);
+        int64_t* c = lvl(k);
+        for (int64_t j = 0; j <= (int64_t(1) << k); ++j) c[j] = leaf_bounds[j * step];
+    }
+    return true;
+}
+
+struct HBlock {
+    int level;
+    int64_t row0, nrows, col0, ncols;
+};
+
+std::vector<HBlock> build_blocks(int depth, const std::vector<int64_t>& bounds) {
+    std::vector<HBlock> out;
+    for (int k = 1; k <= depth; ++k) {
+        const int64_t* b = bounds.data() + ((int64_t(1) << k) - 1) + k;
+        for (int64_t j = 0; j < (int64_t(1) << k); ++j) {
+            const int64_t c = j ^ 1;
+            out.push_back({k, b[j], b[j + 1] - b[j], b[c], b[c + 1] - b[c]});
+        }
+    }
+    return out;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// operator
+// ---------------------------------------------------------------------------
+struct Workspace {
+    double* partial = nullptr;
+    double* T = nullptr;
+    void* xpad = nullptr;
+    int64_t cap_partial = 0, cap_T = 0, cap_xpad = 0;
+};
+
+struct hodlr_op_s {
+    int64_t n = 0;
+    int depth = 0;
+    int nb = 0;
+    int nleaves = 0;
+    std::vector<int64_t> bounds;
+    std::vector<HBlock> blocks;
+    std::vector<int32_t> rank;
+    std::vector<std::vector<double>> U, V, D;   // fp64, column-major, ld = rows
+
+    // assignment
+    std::vector<int32_t> level_fmt;            // per level k-1
+    std::vector<double> xi, uprime;
+    std::vector<int32_t> insufficient;
+    double eps = 0.0;
+    bool acc_double = true;
+    bool scale_cols = true;
+
+    // padded layout
+    std::vector<int64_t> lprow0, lmp;          // per leaf
+    int64_t npad = 0;
+    bool padded = false;
+
+    // host-side descriptors (mirrors of the device arrays)
+    std::vector<BlockDesc> bdesc;
+    std::vector<LeafDesc> ldesc;
+    std::vector<CItem> citems;
+    std::vector<ETile> etiles;
+    int64_t fac_bytes = 0;     // device factor buffer size
+    int64_t total_rank = 0;    // sum of ranks (T slots)
+    int64_t total_item_rank = 0;
+    int64_t codes_bytes = 0;   // sum (r+c) p s(f)
+    int64_t scaled_cols = 0;
+
+    // device
+    int device = -1;
+    uint8_t* d_fac = nullptr;
+    double* d_leaf = nullptr;
+    BlockDesc* d_blocks = nullptr;
+    LeafDesc* d_leaves = nullptr;
+    CItem* d_citems = nullptr;
+    ETile* d_etiles = nullptr;
+    double* d_tscale = nullptr;
+    std::mutex ws_mu;
+    std::map<void*, Workspace> ws;             // per stream
+
+    // per-phase timing (hodlr_profile)
+    std::vector<hipEvent_t> prof_ev;           // 2 * kPhases per record
+    std::vector<uint8_t> prof_ran;             // kPhases per record
+    int32_t prof_cap = 0, prof_used = 0;
+};
+
+namespace {
+
+int64_t node_of(const hodlr_op_s* op, int k, int64_t j, int64_t* b, int64_t* e) {
+    const int64_t* lv = op->bounds.data() + ((int64_t(1) << k) - 1) + k;
+    *b = lv[j];
+    *e = lv[j + 1];
+    return *e - *b;
+}
+
+// Padded row range of node j at level k: its leaves are
+// [j 2^(depth-k), (j+1) 2^(depth-k)).
+void node_padded(const hodlr_op_s* op, int k, int64_t j, int64_t* prow0, int64_t* prows) {
+    const int64_t step = int64_t(1) << (op->depth - k);
+    const int64_t l0 = j * step, l1 = (j + 1) * step;
+    *prow0 = op->lprow0[l0];
+    *prows = op->lprow0[l1 - 1] + op->lmp[l1 - 1] - *prow0;
+}
+
+void dev_free(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+void free_profile(hodlr_op_s* op) {
+    for (hipEvent_t e : op->prof_ev) (void)hipEventDestroy(e);
+    op->prof_ev.clear();
+    op->prof_ran.clear();
+    op->prof_cap = op->prof_used = 0;
+}
+
+void free_device(hodlr_op_s* op) {
+    free_profile(op);
+    dev_free(op->d_fac);
+    dev_free(op->d_leaf);
+    dev_free(op->d_blocks);
+    dev_free(op->d_leaves);
+    dev_free(op->d_citems);
+    dev_free(op->d_etiles);
+    dev_free(op->d_tscale);
+    op->d_fac = nullptr;
+    op->d_leaf = nullptr;
+    op->d_blocks = nullptr;
+    op->d_leaves = nullptr;
+    op->d_citems = nullptr;
+    op->d_etiles = nullptr;
+    op->d_tscale = nullptr;
+    for (auto& kv : op->ws) {
+        dev_free(kv.second.partial);
+        dev_free(kv.second.T);
+        dev_free(kv.second.xpad);
+    }
+    op->ws.clear();
+}
+
+hodlr_status hip_fail(hipError_t e, const char* what) {
+    return fail(HODLR_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <typename T>
+hodlr_status upload(T** dst, const T* src, size_t count, const char* what) {
+    dev_free(*dst);
+    *dst = nullptr;
+    if (count == 0) return HODLR_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), count * sizeof(T));
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        (void)hipGetLastError();
+        return fail(HODLR_E_NOMEM, "hipMalloc %s (%zu bytes): %s", what, count * sizeof(T),
+                    hipGetErrorString(e));
+    }
+    e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, what);
+    return HODLR_OK;
+}
+
+// Chunk rows of a contraction work item: aim at ~64 KB of codes per item,
+// in multiples of 256 rows (one wave of 64 lanes x 4 rows).
+int32_t item_rows(int rank, int f) {
+    const int64_t per_row = int64_t(rank) * fmt_bytes(f);
+    int64_t g = per_row > 0 ? (64 * 1024) / (256 * per_row) : 16;
+    g = std::max<int64_t>(1, std::min<int64_t>(16, g));
+    return int32_t(256 * g);
+}
+
+// Quantise block b's factor F (rows x p, fp64, ld = rows) in format f;
+// write codes at (code_of(i, j)) through `put` and the column exponents.
+template <typename Put>
+hodlr_status quantize_factor(const std::vector<double>& Fm, int64_t rows, int p, int f,
+                             bool scale, int32_t* exps, Put put) {
+    for (int j = 0; j < p; ++j) {
+        const double* col = Fm.data() + int64_t(j) * rows;
+        int e = 0;
+        if (scale && scaled_format(f)) {
+            double amax = 0.0;
+            for (int64_t i = 0; i < rows; ++i) amax = std::max(amax, std::fabs(col[i]));
+            e = column_exponent(f, amax);
+            if (e < -128 || e > 127)
+                return fail(HODLR_E_RANGE, "column scale exponent %d out of int8 range", e);
+        }
+        exps[j] = e;
+        bool ovf = false;
+        for (int64_t i = 0; i < rows; ++i) put(i, j, encode_rne(std::ldexp(col[i], e), f, &ovf));
+        if (ovf)
+            return fail(HODLR_E_RANGE, "a factor value overflows the storage format (column %d)", j);
+    }
+    return HODLR_OK;
+}
+
+void put_code(uint8_t* dst, int f, uint64_t code) {
+    switch (fmt_bytes(f)) {
+        case 8: std::memcpy(dst, &code, 8); break;
+        case 4: { uint32_t c = uint32_t(code); std::memcpy(dst, &c, 4); } break;
+        case 2: { uint16_t c = uint16_t(code); std::memcpy(dst, &c, 2); } break;
+        default: *dst = uint8_t(code); break;
+    }
+}
+
+// Padded row (relative to the node start) of unpadded row r (relative to the
+// node's first index) for node j of level k.
+struct RowMap {
+    std::vector<int64_t> pr;   // padded offset of every row of the node
+};
+
+void node_rowmap(const hodlr_op_s* op, int k, int64_t j, std::vector<int64_t>& out) {
+    int64_t b, e;
+    node_of(op, k, j, &b, &e);
+    out.resize(size_t(e - b));
+    const int64_t step = int64_t(1) << (op->depth - k);
+    const int64_t p0 = op->lprow0[j * step];
+    const int64_t* lb = op->bounds.data() + ((int64_t(1) << op->depth) - 1) + op->depth;
+    int64_t idx = 0;
+    for (int64_t l = j * step; l < (j + 1) * step; ++l) {
+        const int64_t m = lb[l + 1] - lb[l];
+        for (int64_t r = 0; r < m; ++r) out[size_t(idx++)] = op->lprow0[l] - p0 + r;
+    }
+}
+
+// Build descriptors, quantise every factor into a host staging image and
+// (for device handles) upload it.  Called after create and after every
+// precision change.
+hodlr_status pack(hodlr_op_s* op) {
+    const int nb = op->nb;
+    op->bdesc.assign(nb, BlockDesc{});
+    op->citems.clear();
+    int64_t off = 0, toff = 0, poff = 0;
+    op->codes_bytes = 0;
+    op->scaled_cols = 0;
+    std::vector<int64_t> ts_off(nb);
+    int64_t ts_total = 0;
+    for (int b = 0; b < nb; ++b) {
+        const HBlock& hb = op->blocks[b];
+        const int k = hb.level;
+        const int64_t j = b - ((int64_t(1) << k) - 2);
+        BlockDesc& d = op->bdesc[b];
+        const int f = op->level_fmt[k - 1];
+        const int p = op->rank[b];
+        int64_t up0, upr, vp0, vpr;
+        node_padded(op, k, j, &up0, &upr);
+        node_padded(op, k, j ^ 1, &vp0, &vpr);
+        d.rank = p;
+        d.fmt = f;
+        d.level = k;
+        d.urow0 = int32_t(up0);
+        d.urows = int32_t(upr);
+        d.vrow0 = int32_t(vp0);
+        d.vrows = int32_t(vpr);
+        d.u_off = off;
+        off = align_up(off + upr * p * fmt_bytes(f), kPanelAlign);
+        d.v_off = off;
+        off = align_up(off + vpr * p * fmt_bytes(f), kPanelAlign);
+        d.t_off = toff;
+        toff += p;
+        d.ts_off = ts_total;
+        ts_off[b] = ts_total;
+        ts_total += p;
+        d.item0 = int32_t(op->citems.size());
+        if (p > 0) {
+            const int32_t ch = item_rows(p, f);
+            for (int64_t r = 0; r < vpr; r += ch) {
+                CItem it{};
+                it.block = b;
+                it.r0 = int32_t(r);
+                it.nr = int32_t(std::min<int64_t>(ch, vpr - r));
+                it.poff = poff;
+                poff += p;
+                op->citems.push_back(it);
+            }
+        }
+        d.nitems = int32_t(op->citems.size()) - d.item0;
+        op->codes_bytes += (hb.nrows + hb.ncols) * p * fmt_bytes(f);
+        if (op->scale_cols && scaled_format(f)) op->scaled_cols += 2 * p;
+    }
+    op->fac_bytes = std::max<int64_t>(off, kPanelAlign);
+    op->total_rank = toff;
+    op->total_item_rank = poff;
+
+    std::vector<uint8_t> img;
+    try {
+        img.assign(size_t(op->fac_bytes), 0);
+    } catch (const std::bad_alloc&) {
+        return fail(HODLR_E_NOMEM, "host staging image of %lld bytes", (long long)op->fac_bytes);
+    }
+    std::vector<double> tscale(size_t(std::max<int64_t>(ts_total, 1)), 1.0);
+    std::vector<hodlr_status> st(nb, HODLR_OK);
+    std::vector<std::string> msg(nb);
+    parallel_for(nb, [&](int64_t b) {
+        const HBlock& hb = op->blocks[b];
+        const BlockDesc& d = op->bdesc[b];
+        const int p = d.rank;
+        if (p == 0) return;
+        const int k = hb.level;
+        const int64_t j = b - ((int64_t(1) << k) - 2);
+        const int f = d.fmt;
+        const int s = fmt_bytes(f);
+        std::vector<int64_t> umap, vmap;
+        node_rowmap(op, k, j, umap);
+        node_rowmap(op, k, j ^ 1, vmap);
+        std::vector<int32_t> eu(p), ev(p);
+        uint8_t* ub = img.data() + d.u_off;
+        uint8_t* vb = img.data() + d.v_off;
+        hodlr_status r = quantize_factor(op->U[b], hb.nrows, p, f, op->scale_cols, eu.data(),
+                                         [&](int64_t i, int jj, uint64_t c) {
+                                             put_code(ub + (int64_t(jj) * d.urows + umap[i]) * s, f, c);
+                                         });
+        if (r == HODLR_OK)
+            r = quantize_factor(op->V[b], hb.ncols, p, f, op->scale_cols, ev.data(),
+                                [&](int64_t i, int jj, uint64_t c) {
+                                    put_code(vb + (int64_t(jj) * d.vrows + vmap[i]) * s, f, c);
+                                });
+        if (r != HODLR_OK) {
+            st[b] = r;
+            msg[b] = g_last_error;
+            return;
+        }
+        // e4m3 codes are decoded through fp16 at 2^-8 of their value
+        const int comp = (f == E4M3) ? 16 : 0;
+        for (int jj = 0; jj < p; ++jj)
+            tscale[size_t(ts_off[b] + jj)] = std::ldexp(1.0, comp - eu[jj] - ev[jj]);
+    });
+    for (int b = 0; b < nb; ++b)
+        if (st[b] != HODLR_OK) return fail(st[b], "%s", msg[b].c_str());
+
+    if (op->device < 0) return HODLR_OK;
+    hipError_t e = hipSetDevice(op->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hodlr_status r;
+    if ((r = upload(&op->d_fac, img.data(), img.size(), "factor image")) != HODLR_OK) return r;
+    if ((r = upload(&op->d_blocks, op->bdesc.data(), op->bdesc.size(), "block table")) != HODLR_OK)
+        return r;
+    if ((r = upload(&op->d_citems, op->citems.data(), op->citems.size(), "work items")) != HODLR_OK)
+        return r;
+    if ((r = upload(&op->d_tscale, tscale.data(), tscale.size(), "column scales")) != HODLR_OK)
+        return r;
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "upload");
+    return HODLR_OK;
+}
+
+// Leaves and tiles: once per operator.
+hodlr_status pack_leaves(hodlr_op_s* op) {
+    const int nl = op->nleaves;
+    const int64_t* lb = op->bounds.data() + ((int64_t(1) << op->depth) - 1) + op->depth;
+    op->lprow0.assign(nl, 0);
+    op->lmp.assign(nl, 0);
+    int64_t pr = 0;
+    op->padded = false;
+    for (int i = 0; i < nl; ++i) {
+        const int64_t m = lb[i + 1] - lb[i];
+        op->lprow0[i] = pr;
+        op->lmp[i] = align_up(m, kRowAlign);
+        if (op->lmp[i] != m) op->padded = true;
+        pr += op->lmp[i];
+    }
+    op->npad = pr;
+    if (op->npad >= (int64_t(1) << 31))
+        return fail(HODLR_E_UNSUPPORTED, "padded size %lld exceeds 2^31 rows", (long long)pr);
+    op->ldesc.assign(nl, LeafDesc{});
+    op->etiles.clear();
+    int64_t doff = 0;
+    for (int i = 0; i < nl; ++i) {
+        LeafDesc& L = op->ldesc[i];
+        L.d_off = doff;
+        L.row0 = lb[i];
+        L.m = int32_t(lb[i + 1] - lb[i]);
+        L.mp = int32_t(op->lmp[i]);
+        L.prow0 = int32_t(op->lprow0[i]);
+        doff += int64_t(L.mp) * L.mp;
+        for (int32_t r = 0; r < L.mp; r += 256) {
+            ETile t{};
+            t.leaf = i;
+            t.r0 = r;
+            t.nr = std::min<int32_t>(256, L.mp - r);
+            op->etiles.push_back(t);
+        }
+    }
+    if (op->device < 0) return HODLR_OK;
+    std::vector<double> img;
+    try {
+        img.assign(size_t(std::max<int64_t>(doff, 1)), 0.0);
+    } catch (const std::bad_alloc&) {
+        return fail(HODLR_E_NOMEM, "host staging of leaves");
+    }
+    parallel_for(nl, [&](int64_t i) {
+        const LeafDesc& L = op->ldesc[i];
+        for (int64_t c = 0; c < L.m; ++c)
+            std::memcpy(img.data() + L.d_off + c * L.mp, op->D[i].data() + c * L.m,
+                        sizeof(double) * size_t(L.m));
+    });
+    hipError_t e = hipSetDevice(op->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hodlr_status r;
+    if ((r = upload(&op->d_leaf, img.data(), img.size(), "leaf blocks")) != HODLR_OK) return r;
+    if ((r = upload(&op->d_leaves, op->ldesc.data(), op->ldesc.size(), "leaf table")) != HODLR_OK)
+        return r;
+    if ((r = upload(&op->d_etiles, op->etiles.data(), op->etiles.size(), "tiles")) != HODLR_OK)
+        return r;
+    return HODLR_OK;
+}
+
+bool valid_fmt(int32_t f) { return f >= 0 && f < NFMT; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int32_t hodlr_depth_for_leaf(int64_t n, int64_t leaf) {
+    if (n < 1 || leaf < 1) return -1;
+    int32_t d = 0;
+    while (leaf * (int64_t(1) << d) < n) ++d;
+    return d;
+}
+
+hodlr_status hodlr_tree_bounds(int64_t n, int32_t depth, const int64_t* leaf_bounds,
+                               int64_t* bounds_out) {
+    if (n < 1 || depth < 0 || depth > 24 || !bounds_out)
+        return fail(HODLR_E_ARG, "hodlr_tree_bounds: n >= 1, 0 <= depth <= 24, non-null output");
+    std::vector<int64_t> b;
+    if (!build_bounds(n, depth, leaf_bounds, b))
+        return fail(HODLR_E_ARG, "leaf_bounds must run non-decreasing from 0 to n");
+    std::memcpy(bounds_out, b.data(), b.size() * sizeof(int64_t));
+    return ok();
+}
+
+hodlr_status hodlr_tree_blocks(int64_t n, int32_t depth, const int64_t* leaf_bounds,
+                               int64_t* desc_out) {
+    if (n < 1 || depth < 0 || depth > 24 || !desc_out)
+        return fail(HODLR_E_ARG, "hodlr_tree_blocks: n >= 1, 0 <= depth <= 24, non-null output");
+    std::vector<int64_t> b;
+    if (!build_bounds(n, depth, leaf_bounds, b))
+        return fail(HODLR_E_ARG, "leaf_bounds must run non-decreasing from 0 to n");
+    const auto blks = build_blocks(depth, b);
+    for (size_t i = 0; i < blks.size(); ++i) {
+        desc_out[5 * i + 0] = blks[i].level;
+        desc_out[5 * i + 1] = blks[i].row0;
+        desc_out[5 * i + 2] = blks[i].nrows;
+        desc_out[5 * i + 3] = blks[i].col0;
+        desc_out[5 * i + 4] = blks[i].ncols;
+    }
+    return ok();
+}
+
+hodlr_status hodlr_create(hodlr_op* out, int64_t n, int32_t depth, const int64_t* leaf_bounds,
+                          const double* const* leaves, const int64_t* ld_leaves,
+                          const hodlr_lowrank* blocks, int32_t device) {
+    if (!out) return fail(HODLR_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || depth < 0 || depth > 24)
+        return fail(HODLR_E_ARG, "need n >= 1 and 0 <= depth <= 24");
+    if (!leaves || !ld_leaves || (depth > 0 && !blocks))
+        return fail(HODLR_E_ARG, "leaves, ld_leaves and blocks must be non-null");
+    if (device < -1) return fail(HODLR_E_ARG, "device must be >= -1");
+    std::unique_ptr<hodlr_op_s> op(new (std::nothrow) hodlr_op_s);
+    if (!op) return fail(HODLR_E_NOMEM, "operator");
+    op->n = n;
+    op->depth = depth;
+    op->nleaves = 1 << depth;
+    op->nb = (1 << (depth + 1)) - 2;
+    if (!build_bounds(n, depth, leaf_bounds, op->bounds))
+        return fail(HODLR_E_ARG, "leaf_bounds must run non-decreasing from 0 to n");
+    op->blocks = build_blocks(depth, op->bounds);
+    const int64_t* lb = op->bounds.data() + ((int64_t(1) << depth) - 1) + depth;
+    try {
+        op->D.resize(op->nleaves);
+        for (int i = 0; i < op->nleaves; ++i) {
+            const int64_t m = lb[i + 1] - lb[i];
+            if (m > 0 && (!leaves[i] || ld_leaves[i] < m))
+                return fail(HODLR_E_ARG, "leaf %d: NULL data or ld < m", i);
+            op->D[i].resize(size_t(m * m));
+            for (int64_t c = 0; c < m; ++c)
+                std::memcpy(op->D[i].data() + c * m, leaves[i] + c * ld_leaves[i], sizeof(double) * m);
+        }
+        op->U.resize(op->nb);
+        op->V.resize(op->nb);
+        op->rank.resize(op->nb);
+        for (int b = 0; b < op->nb; ++b) {
+            const HBlock& hb = op->blocks[b];
+            const hodlr_lowrank& L = blocks[b];
+            if (L.rank < 0 || L.rank > std::min(hb.nrows, hb.ncols))
+                return fail(HODLR_E_ARG, "block %d: rank %d outside [0, min(%lld, %lld)]", b,
+                            L.rank, (long long)hb.nrows, (long long)hb.ncols);
+            if (L.rank > 0 && (!L.U || !L.V || L.ldu < hb.nrows || L.ldv < hb.ncols))
+                return fail(HODLR_E_ARG, "block %d: NULL factor or leading dimension too small", b);
+            op->rank[b] = L.rank;
+            op->U[b].resize(size_t(hb.nrows * L.rank));
+            op->V[b].resize(size_t(hb.ncols * L.rank));
+            for (int j = 0; j < L.rank; ++j) {
+                std::memcpy(op->U[b].data() + j * hb.nrows, L.U + j * L.ldu, sizeof(double) * hb.nrows);
+                std::memcpy(op->V[b].data() + j * hb.ncols, L.V + j * L.ldv, sizeof(double) * hb.ncols);
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(HODLR_E_NOMEM, "host copy of the operator");
+    }
+    op->level_fmt.assign(depth, F64);
+    op->xi.assign(depth, 0.0);
+    op->uprime.assign(depth, 0.0);
+    op->insufficient.assign(depth, 0);
+    op->acc_double = true;
+    op->device = device;
+    if (device >= 0) {
+        int cnt = 0;
+        hipError_t e = hipGetDeviceCount(&cnt);
+        if (e != hipSuccess || device >= cnt)
+            return fail(HODLR_E_DEVICE, "device %d not available (%d devices): %s", device, cnt,
+                        hipGetErrorString(e));
+    }
+    hodlr_status r = pack_leaves(op.get());
+    if (r == HODLR_OK) r = pack(op.get());
+    if (r != HODLR_OK) {
+        free_device(op.get());
+        return r;
+    }
+    *out = op.release();
+    return ok();
+}
+
+hodlr_status hodlr_assign_precision(hodlr_op op, double eps, const int32_t* allowed,
+                                    int32_t n_allowed, const double* norms2, uint32_t flags) {
+    if (!op) return fail(HODLR_E_ARG, "op is NULL");
+    if (!(eps > 0.0 && eps < 1.0)) return fail(HODLR_E_ARG, "eps must lie in (0, 1)");
+    if (n_allowed < 0 || (n_allowed > 0 && !allowed)) return fail(HODLR_E_ARG, "allowed set");
+    for (int i = 0; i < n_allowed; ++i)
+        if (!valid_fmt(allowed[i])) return fail(HODLR_E_ARG, "allowed[%d] = %d is no format", i, allowed[i]);
+    if ((flags & HODLR_ACC_FP32) && (flags & HODLR_ACC_FP64))
+        return fail(HODLR_E_ARG, "HODLR_ACC_FP32 and HODLR_ACC_FP64 both set");
+    const int depth = op->depth;
+    // nrmAll and per-level maxima of ||H_b||_F^2
+    double all = 0.0;
+    std::vector<double> lvl(depth, 0.0);
+    if (norms2) {
+        all = norms2[0];
+        for (int b = 0; b < op->nb; ++b) {
+            const double v = norms2[1 + b];
+            if (!(v >= 0.0)) return fail(HODLR_E_ARG, "norms2[%d] is negative or NaN", 1 + b);
+            lvl[op->blocks[b].level - 1] = std::max(lvl[op->blocks[b].level - 1], v);
+        }
+        if (!(all >= 0.0)) return fail(HODLR_E_ARG, "norms2[0] is negative or NaN");
+    } else {
+        // ||U V^T||_F^2 = sum((U^T U) .* (V^T V)); ||H~||_F^2 adds the leaves
+        std::vector<double> nb2(op->nb, 0.0);
+        parallel_for(op->nb, [&](int64_t b) {
+            const int p = op->rank[b];
+            const int64_t r = op->blocks[b].nrows, c = op->blocks[b].ncols;
+            double s = 0.0;
+            for (int a = 0; a < p; ++a)
+                for (int bb = 0; bb < p; ++bb) {
+                    double gu = 0.0, gv = 0.0;
+                    for (int64_t i = 0; i < r; ++i) gu += op->U[b][a * r + i] * op->U[b][bb * r + i];
+                    for (int64_t i = 0; i < c; ++i) gv += op->V[b][a * c + i] * op->V[b][bb * c + i];
+                    s += gu * gv;
+                }
+            nb2[b] = s;
+        });
+        for (int i = 0; i < op->nleaves; ++i)
+            for (double v : op->D[i]) all += v * v;
+        for (int b = 0; b < op->nb; ++b) {
+            all += nb2[b];
+            lvl[op->blocks[b].level - 1] = std::max(lvl[op->blocks[b].level - 1], nb2[b]);
+        }
+    }
+    // candidates: fp64 (the working precision) and the allowed set
+    std::vector<int> cand = {F64};
+    for (int i = 0; i < n_allowed; ++i) cand.push_back(allowed[i]);
+    std::vector<int32_t> fmt(depth), bad(depth);
+    std::vector<double> xi(depth), up(depth);
+    for (int k = 1; k <= depth; ++k) {
+        const double x = all > 0.0 ? std::sqrt(lvl[k - 1] / all) : 0.0;
+        const double u1 = (x == 0.0) ? INFINITY : eps / (std::sqrt(std::ldexp(1.0, k)) * x);
+        int best = -1;
+        for (int f : cand)
+            if (unit_roundoff(f) <= u1 && (best < 0 || unit_roundoff(f) > unit_roundoff(best))) best = f;
+        xi[k - 1] = x;
+        up[k - 1] = u1;
+        fmt[k - 1] = best < 0 ? F64 : best;
+        bad[k - 1] = best < 0 ? 1 : 0;
+    }
+    const auto old_fmt = op->level_fmt;
+    const bool old_acc = op->acc_double, old_scale = op->scale_cols;
+    op->level_fmt = fmt;
+    op->scale_cols = !(flags & HODLR_NO_COLUMN_SCALE);
+    op->acc_double = (flags & HODLR_ACC_FP64) ? true : (flags & HODLR_ACC_FP32) ? false : (eps < 1e-7);
+    hodlr_status r = pack(op);
+    if (r != HODLR_OK) {
+        std::string m = g_last_error;
+        op->level_fmt = old_fmt;
+        op->acc_double = old_acc;
+        op->scale_cols = old_scale;
+        (void)pack(op);
+        return fail(r, "%s", m.c_str());
+    }
+    op->xi = xi;
+    op->uprime = up;
+    op->insufficient = bad;
+    op->eps = eps;
+    return ok();
+}
+
+hodlr_status hodlr_set_level_precisions(hodlr_op op, const int32_t* per_level, uint32_t flags) {
+    if (!op) return fail(HODLR_E_ARG, "op is NULL");
+    if (op->depth > 0 && !per_level) return fail(HODLR_E_ARG, "per_level is NULL");
+    if ((flags & HODLR_ACC_FP32) && (flags & HODLR_ACC_FP64))
+        return fail(HODLR_E_ARG, "HODLR_ACC_FP32 and HODLR_ACC_FP64 both set");
+    bool all64 = true;
+    for (int k = 0; k < op->depth; ++k) {
+        if (!valid_fmt(per_level[k])) return fail(HODLR_E_ARG, "per_level[%d] = %d is no format", k, per_level[k]);
+        all64 = all64 && per_level[k] == F64;
+    }
+    const auto old_fmt = op->level_fmt;
+    const bool old_acc = op->acc_double, old_scale = op->scale_cols;
+    op->level_fmt.assign(per_level, per_level + op->depth);
+    op->scale_cols = !(flags & HODLR_NO_COLUMN_SCALE);
+    op->acc_double = (flags & HODLR_ACC_FP64) ? true : (flags & HODLR_ACC_FP32) ? false : all64;
+    hodlr_status r = pack(op);
+    if (r != HODLR_OK) {
+        std::string m = g_last_error;
+        op->level_fmt = old_fmt;
+        op->acc_double = old_acc;
+        op->scale_cols = old_scale;
+        (void)pack(op);
+        return fail(r, "%s", m.c_str());
+    }
+    op->xi.assign(op->depth, 0.0);
+    op->uprime.assign(op->depth, 0.0);
+    op->insufficient.assign(op->depth, 0);
+    op->eps = 0.0;
+    return ok();
+}
+
+hodlr_status hodlr_get_level(hodlr_op op, int32_t level, int32_t* dtype, double* xi,
+                             double* u_prime, int32_t* insufficient) {
+    if (!op) return fail(HODLR_E_ARG, "op is NULL");
+    if (level < 1 || level > op->depth) return fail(HODLR_E_ARG, "level %d outside 1..%d", level, op->depth);
+    if (dtype) *dtype = op->level_fmt[level - 1];
+    if (xi) *xi = op->xi[level - 1];
+    if (u_prime) *u_prime = op->uprime[level - 1];
+    if (insufficient) *insufficient = op->insufficient[level - 1];
+    return ok();
+}
+
+hodlr_status hodlr_get_info(hodlr_op op, hodlr_info* info) {
+    if (!op || !info) return fail(HODLR_E_ARG, "NULL argument");
+    info->n = op->n;
+    info->depth = op->depth;
+    info->nblocks = op->nb;
+    info->acc_dtype = op->acc_double ? HODLR_FP64 : HODLR_FP32;
+    info->max_rank = 0;
+    for (int32_t r : op->rank) info->max_rank = std::max(info->max_rank, r);
+    info->on_device = op->device >= 0;
+    info->device = op->device;
+    info->eps = op->eps;
+    int64_t lb = 0;
+    for (auto& d : op->D) lb += int64_t(d.size()) * 8;
+    info->leaf_bytes = lb;
+    info->factor_bytes = op->codes_bytes;
+    info->scale_bytes = op->scaled_cols;
+    int64_t dl = 0;
+    for (auto& L : op->ldesc) dl += int64_t(L.mp) * L.mp * 8;
+    info->device_bytes = op->fac_bytes + dl;
+    return ok();
+}
+
+hodlr_status hodlr_get_block(hodlr_op op, int32_t block, hodlr_block_info* info) {
+    if (!op || !info) return fail(HODLR_E_ARG, "NULL argument");
+    if (block < 0 || block >= op->nb) return fail(HODLR_E_ARG, "block %d outside 0..%d", block, op->nb - 1);
+    const HBlock& hb = op->blocks[block];
+    info->level = hb.level;
+    info->rank = op->rank[block];
+    info->row0 = hb.row0;
+    info->nrows = hb.nrows;
+    info->col0 = hb.col0;
+    info->ncols = hb.ncols;
+    info->dtype = op->level_fmt[hb.level - 1];
+    info->scaled = (op->scale_cols && scaled_format(info->dtype)) ? 1 : 0;
+    return ok();
+}
+
+hodlr_status hodlr_export_block(hodlr_op op, int32_t block, void* u_codes, int8_t* u_exp,
+                                void* v_codes, int8_t* v_exp, int32_t from_device) {
+    if (!op) return fail(HODLR_E_ARG, "op is NULL");
+    if (block < 0 || block >= op->nb) return fail(HODLR_E_ARG, "block %d outside 0..%d", block, op->nb - 1);
+    const HBlock& hb = op->blocks[block];
+    const BlockDesc& d = op->bdesc[block];
+    const int p = d.rank, f = d.fmt, s = fmt_bytes(f);
+    const int k = hb.level;
+    const int64_t j = block - ((int64_t(1) << k) - 2);
+    std::vector<int32_t> eu(p), ev(p);
+    std::vector<int64_t> umap, vmap;
+    node_rowmap(op, k, j, umap);
+    node_rowmap(op, k, j ^ 1, vmap);
+    auto put_u = [&](int64_t i, int jj, uint64_t c) {
+        if (u_codes) put_code(static_cast<uint8_t*>(u_codes) + (int64_t(jj) * hb.nrows + i) * s, f, c);
+    };
+    auto put_v = [&](int64_t i, int jj, uint64_t c) {
+        if (v_codes) put_code(static_cast<uint8_t*>(v_codes) + (int64_t(jj) * hb.ncols + i) * s, f, c);
+    };
+    hodlr_status r = quantize_factor(op->U[block], hb.nrows, p, f, op->scale_cols, eu.data(), put_u);
+    if (r == HODLR_OK) r = quantize_factor(op->V[block], hb.ncols, p, f, op->scale_cols, ev.data(), put_v);
+    if (r != HODLR_OK) return r;
+    if (from_device) {
+        if (op->device < 0 || !op->d_fac) return fail(HODLR_E_STATE, "host-only handle has no device image");
+        hipError_t e = hipSetDevice(op->device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+        std::vector<uint8_t> ub(size_t(d.urows) * p * s), vb(size_t(d.vrows) * p * s);
+        if (p > 0) {
+            e = hipMemcpy(ub.data(), op->d_fac + d.u_off, ub.size(), hipMemcpyDeviceToHost);
+            if (e == hipSuccess)
+                e = hipMemcpy(vb.data(), op->d_fac + d.v_off, vb.size(), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "read back factor image");
+        }
+        for (int jj = 0; jj < p; ++jj) {
+            if (u_codes)
+                for (int64_t i = 0; i < hb.nrows; ++i)
+                    std::memcpy(static_cast<uint8_t*>(u_codes) + (int64_t(jj) * hb.nrows + i) * s,
+                                ub.data() + (int64_t(jj) * d.urows + umap[i]) * s, s);
+            if (v_codes)
+                for (int64_t i = 0; i < hb.ncols; ++i)
+                    std::memcpy(static_cast<uint8_t*>(v_codes) + (int64_t(jj) * hb.ncols + i) * s,
+                                vb.data() + (int64_t(jj) * d.vrows + vmap[i]) * s, s);
+        }
+    }
+    for (int jj = 0; jj < p; ++jj) {
+        if (u_exp) u_exp[jj] = int8_t(eu[jj]);
+        if (v_exp) v_exp[jj] = int8_t(ev[jj]);
+    }
+    return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_double, KParams* kp) {
+    std::lock_guard<std::mutex> lk(op->ws_mu);
+    Workspace& w = op->ws[stream];
+    const int64_t need_p = std::max<int64_t>(1, op->total_item_rank * nrhs);
+    const int64_t need_t = std::max<int64_t>(1, op->total_rank * nrhs);
+    const int64_t need_x = op->padded ? op->npad * nrhs * (xy_double ? 8 : 4) : 0;
+    auto grow = [&](void** ptr, int64_t* cap, int64_t bytes, const char* what) -> hodlr_status {
+        if (bytes <= *cap) return HODLR_OK;
+        if (*ptr) {
+            hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            dev_free(*ptr);
+            *ptr = nullptr;
+            *cap = 0;
+        }
+        hipError_t e = hipMalloc(ptr, size_t(bytes));
+        if (e != hipSuccess) {
+            *ptr = nullptr;
+            (void)hipGetLastError();
+            return fail(HODLR_E_NOMEM, "workspace %s (%lld bytes)", what, (long long)bytes);
+        }
+        *cap = bytes;
+        return HODLR_OK;
+    };
+    hodlr_status r;
+    if ((r = grow(reinterpret_cast<void**>(&w.partial), &w.cap_partial, need_p * 8, "partials")) != HODLR_OK)
+        return r;
+    if ((r = grow(reinterpret_cast<void**>(&w.T), &w.cap_T, need_t * 8, "T")) != HODLR_OK) return r;
+    if (need_x && (r = grow(&w.xpad, &w.cap_xpad, need_x, "padded X")) != HODLR_OK) return r;
+    kp->fac = op->d_fac;
+    kp->leafd = op->d_leaf;
+    kp->blocks = op->d_blocks;
+    kp->leaves = op->d_leaves;
+    kp->citems = op->d_citems;
+    kp->etiles = op->d_etiles;
+    kp->tscale = op->d_tscale;
+    kp->partial = w.partial;
+    kp->T = w.T;
+    kp->xpad = w.xpad;
+    kp->npad = op->npad;
+    kp->depth = op->depth;
+    kp->nblocks = op->nb;
+    kp->nleaves = op->nleaves;
+    kp->ncitems = int32_t(op->citems.size());
+    kp->netiles = int32_t(op->etiles.size());
+    kp->padded = op->padded ? 1 : 0;
+    return HODLR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                          int32_t nrhs, int32_t xy_dtype, void* stream) {
+    if (!op) return fail(HODLR_E_ARG, "op is NULL");
+    if (op->device < 0) return fail(HODLR_E_STATE, "host-only handle: no product");
+    if (nrhs < 1) return fail(HODLR_E_ARG, "nrhs must be >= 1");
+    if (xy_dtype != HODLR_FP32 && xy_dtype != HODLR_FP64)
+        return fail(HODLR_E_UNSUPPORTED, "X/Y dtype must be HODLR_FP32 or HODLR_FP64");
+    if (!X || !Y) return fail(HODLR_E_ARG, "X or Y is NULL");
+    if (ldx < op->n || ldy < op->n) return fail(HODLR_E_ARG, "ldx and ldy must be >= n");
+    hipError_t e = hipSetDevice(op->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    KParams kp{};
+    hodlr_status r = prepare_workspace(op, stream, nrhs, xy_dtype == HODLR_FP64, &kp);
+    if (r != HODLR_OK) return r;
+    void* const* ev = nullptr;
+    bool ran[kPhases] = {false, false, false, false};
+    int32_t slot = -1;
+    if (op->prof_used < op->prof_cap) {
+        slot = op->prof_used++;
+        ev = reinterpret_cast<void* const*>(op->prof_ev.data() + size_t(slot) * 2 * kPhases);
+    }
+    const int he = launch_matvec(kp, X, ldx, Y, ldy, nrhs, xy_dtype == HODLR_FP64, op->acc_double, stream,
+                                 ev, ran);
+    if (slot >= 0)
+        for (int ph = 0; ph < kPhases; ++ph) op->prof_ran[size_t(slot) * kPhases + ph] = ran[ph] ? 1 : 0;
+    if (he != 0) return fail(HODLR_E_DEVICE, "kernel launch: %s", hipGetErrorString(hipError_t(he)));
+    return ok();
+}
+
+hodlr_status hodlr_matvec_batched(const hodlr_op* ops, int32_t count, const void* const* X,
+                                  const int64_t* ldx, void* const* Y, const int64_t* ldy,
+                                  const int32_t* nrhs, const int32_t* xy_dtype, void* stream) {
+    if (count < 0) return fail(HODLR_E_ARG, "count < 0");
+    if (count == 0) return ok();
+    if (!ops || !X || !ldx || !Y || !ldy || !nrhs || !xy_dtype) return fail(HODLR_E_ARG, "NULL array");
+    for (int i = 0; i < count; ++i) {
+        if (!ops[i]) return fail(HODLR_E_ARG, "ops[%d] is NULL", i);
+        if (ops[i]->device != ops[0]->device) return fail(HODLR_E_STATE, "operators on different devices");
+    }
+    for (int i = 0; i < count; ++i) {
+        hodlr_status r = hodlr_matvec(ops[i], X[i], ldx[i], Y[i], ldy[i], nrhs[i], xy_dtype[i], stream);
+        if (r != HODLR_OK) return fail(r, "operator %d: %s", i, g_last_error.c_str());
+    }
+    return ok();
+}
+
+hodlr_status hodlr_profile(hodlr_op op, int32_t capacity) {
+    if (!op) return fail(HODLR_E_ARG, "op is NULL");
+    if (capacity < 0) return fail(HODLR_E_ARG, "capacity < 0");
+    if (op->device < 0) return fail(HODLR_E_STATE, "host-only handle");
+    hipError_t e = hipSetDevice(op->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    free_profile(op);
+    if (capacity == 0) return ok();
+    op->prof_ev.resize(size_t(capacity) * 2 * kPhases, nullptr);
+    for (auto& ev : op->prof_ev) {
+        e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+            ev = nullptr;
+            free_profile(op);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    op->prof_ran.assign(size_t(capacity) * kPhases, 0);
+    op->prof_cap = capacity;
+    op->prof_used = 0;
+    return ok();
+}
+
+hodlr_status hodlr_profile_read(hodlr_op op, double* ms_per_phase, int64_t* launches_per_phase) {
+    if (!op || !ms_per_phase || !launches_per_phase) return fail(HODLR_E_ARG, "NULL argument");
+    for (int ph = 0; ph < kPhases; ++ph) {
+        ms_per_phase[ph] = 0.0;
+        launches_per_phase[ph] = 0;
+    }
+    for (int32_t i = 0; i < op->prof_used; ++i)
+        for (int ph = 0; ph < kPhases; ++ph) {
+            if (!op->prof_ran[size_t(i) * kPhases + ph]) continue;
+            hipEvent_t a = op->prof_ev[(size_t(i) * kPhases + ph) * 2];
+            hipEvent_t b = op->prof_ev[(size_t(i) * kPhases + ph) * 2 + 1];
+            hipError_t e = hipEventSynchronize(b);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e != hipSuccess) return hip_fail(e, "reading profile events");
+            ms_per_phase[ph] += ms;
+            launches_per_phase[ph] += 1;
+        }
+    op->prof_used = 0;
+    std::fill(op->prof_ran.begin(), op->prof_ran.end(), 0);
+    return ok();
+}
+
+hodlr_status hodlr_destroy(hodlr_op op) {
+    if (!op) return fail(HODLR_E_ARG, "op is NULL");
+    if (op->device >= 0) {
+        (void)hipSetDevice(op->device);
+        (void)hipDeviceSynchronize();
+    }
+    free_device(op);
+    delete op;
+    return ok();
+}
+
+const char* hodlr_status_string(hodlr_status s) {
+    switch (s) {
+        case HODLR_OK: return "HODLR_OK";
+        case HODLR_E_ARG: return "HODLR_E_ARG";
+        case HODLR_E_STATE: return "HODLR_E_STATE";
+        case HODLR_E_NOMEM: return "HODLR_E_NOMEM";
+        case HODLR_E_DEVICE: return "HODLR_E_DEVICE";
+        case HODLR_E_RANGE: return "HODLR_E_RANGE";
+        case HODLR_E_UNSUPPORTED: return "HODLR_E_UNSUPPORTED";
+    }
+    return "HODLR_E_UNKNOWN";
+}
+
+const char* hodlr_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

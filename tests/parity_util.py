@@ -1,0 +1,88 @@
+"""Shared helpers of the parity tests: build a workload over the oracle's
+partition, run the oracle's stored-operator product, and compare a GPU
+result with it under the componentwise tolerance of ``oracle.bounds``."""
+from __future__ import annotations
+
+import numpy as np
+
+from hodlr_inputs import compress as CP
+from hodlr_inputs import configs as CF
+from oracle import assign as AS
+from oracle import bounds as BD
+from oracle import formats as F
+from oracle import matvec as MV
+from oracle import quantize as Q
+from oracle import tree as T
+
+
+class Case:
+    """A compressed workload plus the oracle's view of it."""
+
+    def __init__(self, cfg, n=None, depth=None, eps=None, leaf_bounds=None, points=None):
+        c = CF.get(cfg) if isinstance(cfg, str) else cfg
+        self.cfg = c
+        self.n = c.n if n is None else n
+        self.depth = c.depth if depth is None else depth
+        self.eps = c.eps if eps is None else eps
+        P = c.points() if points is None else points
+        self.P = P[: self.n]
+        self.leaf_bounds = leaf_bounds
+        self.blocks = T.blocks(self.n, self.depth, leaf_bounds)
+        self.leaves_b = T.leaves(self.n, self.depth, leaf_bounds)
+        na2 = None
+        if c.rule == "spec_global":
+            na2 = float(np.linalg.norm(c.kernel.dense(self.P), 2))
+        self.op = CP.compress(c.kernel, self.P, [(b.row0, b.nrows, b.col0, b.ncols) for b in self.blocks],
+                              self.leaves_b, self.eps, c.rule, na2)
+        self.norms2 = np.concatenate([[self.op.norm2_all], self.op.norm2_blocks])
+
+    def oracle_assign(self, allowed):
+        lv = AS.level_max_norm2(self.op.norm2_blocks, [b.level for b in self.blocks])
+        return AS.assign(self.op.norm2_all, lv, self.eps, allowed)
+
+    def stored(self, level_fmt, scale=True):
+        QU = [Q.quantize(u, level_fmt[b.level - 1], scale) for b, u in zip(self.blocks, self.op.U)]
+        QV = [Q.quantize(v, level_fmt[b.level - 1], scale) for b, v in zip(self.blocks, self.op.V)]
+        return [q.values for q in QU], [q.values for q in QV]
+
+    def oracle_product(self, level_fmt, X, scale=True):
+        U, V = self.stored(level_fmt, scale)
+        y = MV.matvec(self.n, self.blocks, self.leaves_b, self.op.leaves, U, V, X)
+        z = MV.matvec_abs(self.n, self.blocks, self.leaves_b, self.op.leaves, U, V, X)
+        return y, z, U, V
+
+    def chain(self):
+        return BD.chain_length(self.blocks, self.op.ranks, [m for _, m in self.leaves_b], self.depth)
+
+    def library_op(self, device=0):
+        import paper_2407_21637_amd as H
+        return H.Operator(self.n, self.depth, self.op.leaves, self.op.U, self.op.V, device=device,
+                          leaf_bounds=None if self.leaf_bounds is None else
+                          T.node_bounds(self.n, self.depth, self.leaf_bounds)[self.depth])
+
+
+def check(y_gpu, y_ora, z, M, acc, xy, label=""):
+    """Assert both componentwise gates; return error statistics.
+
+    * tau: the worst-case bound (``oracle.bounds.tolerance``);
+    * tau_prob: the probabilistic bound (``oracle.bounds.tolerance_prob``),
+      about sqrt(M) times tighter, met with probability >= 1 - 1e-6 under
+      the model of independent rounding errors.
+    """
+    u_acc = F.FP64.u if acc == "fp64" else F.FP32.u
+    u_out = F.FP64.u if xy == "fp64" else F.FP32.u
+    y_gpu = np.asarray(y_gpu, dtype=np.float64)
+    tau = BD.tolerance(z, y_ora, M, u_acc, u_out)
+    taup = BD.tolerance_prob(z, y_ora, M, u_acc, u_out)
+    err = np.abs(y_gpu - y_ora)
+    nz = lambda t: np.where(t > 0, t, 1)
+    stats = {
+        "max_err_over_tau": float((err / nz(tau)).max()) if err.size else 0.0,
+        "max_err_over_tau_prob": float((err / nz(taup)).max()) if err.size else 0.0,
+        "norm_err_over_uz": float(np.linalg.norm(err) / (u_acc * np.linalg.norm(z))) if err.size else 0.0,
+        "rel_err": float(np.linalg.norm(err) / max(np.linalg.norm(y_ora), 1e-300)),
+    }
+    assert np.isfinite(y_gpu).all(), (label, "non-finite output")
+    assert not (err > tau).any(), (label, int((err > tau).sum()), stats)
+    assert not (err > taup).any(), (label, "prob", int((err > taup).sum()), stats)
+    return stats

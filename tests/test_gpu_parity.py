@@ -1,0 +1,179 @@
+"""GPU parity: the HIP product against the oracle, through the C ABI.
+
+Every case compares the library's Y with the oracle's fp64 product of the
+same stored operator (same fp64 factors, same formats, same codes), entry
+by entry, under the componentwise tolerance of ``oracle.bounds.tolerance``
+(the standard-model bound for a chain of M rounded operations in the
+accumulation precision, plus the output rounding).  Layouts are compared
+bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from tests.parity_util import Case, check  # noqa: E402
+from oracle import bounds as BD  # noqa: E402
+from oracle import quantize as Q  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2407_21637_amd as H  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu_product(h, X, xy):
+    dt = torch.float64 if xy == "fp64" else torch.float32
+    Xt = torch.from_numpy(np.asfortranarray(X)).to(dt)
+    Xd = H.colmajor_empty(X.shape[0], X.shape[1], dt, DEV)
+    Xd.copy_(Xt)
+    Y = h.matvec(Xd)
+    torch.cuda.synchronize()
+    return Y.cpu().double().numpy()
+
+
+def _run(case, h, fmts, nrhs, xy, acc, label, X=None):
+    if X is None:
+        X = case.cfg.X(nrhs)[: case.n] if case.cfg.n >= case.n else None
+        if X is None or X.shape[0] != case.n:
+            rng = np.random.default_rng(1)
+            X = rng.standard_normal((case.n, nrhs))
+        if xy == "fp32":
+            X = X.astype(np.float32).astype(np.float64)
+    _say(f"[parity] {label} n={case.n} depth={case.depth} nrhs={nrhs} fmts={fmts} acc={acc}")
+    y, z, _, _ = case.oracle_product(fmts, X)
+    yg = _gpu_product(h, X, xy)
+    st = check(yg, y, z, case.chain(), acc, xy, label)
+    _say(f"    ok {st}")
+    return X, yg, y, st
+
+
+def test_c1_uniform_fp64_full_size_and_layout():
+    case = Case("c1")
+    h = case.library_op()
+    assert h.info()["acc_dtype"] == "fp64"
+    fm = ["fp64"] * case.depth
+    X, yg, y, _ = _run(case, h, fm, 1, "fp64", "fp64", "c1")
+    # Thm 3.5 against the original matrix (fp64 working precision)
+    A = case.cfg.kernel.dense(case.P)
+    nA = np.sqrt(case.op.norm2_all)
+    eta = np.linalg.norm(yg[:, 0] - A @ X[:, 0]) / (nA * np.linalg.norm(X[:, 0]))
+    assert eta <= BD.matvec_backward_bound(case.depth, case.eps)
+    # the uploaded image equals the oracle's codes bit for bit
+    for b in range(h.nblocks):
+        uc, ue, vc, ve = h.export_block(b, from_device=True)
+        assert np.array_equal(uc, Q.quantize(case.op.U[b], "fp64").codes)
+        assert np.array_equal(vc, Q.quantize(case.op.V[b], "fp64").codes)
+
+
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 8, 17])
+def test_c2_small_adaptive(nrhs):
+    case = Case("c2_s")
+    h = case.library_op()
+    h.assign_precision(case.eps, case.cfg.allowed, case.norms2)
+    a = case.oracle_assign(case.cfg.allowed)
+    assert [lv[0] for lv in h.levels()] == a.fmt
+    _run(case, h, a.fmt, nrhs, "fp32", "fp32", "c2_s")
+
+
+@pytest.mark.parametrize("fmt", ["fp64", "fp32", "bf16", "fp16", "e4m3", "e5m2"])
+def test_forced_format_every_level(fmt):
+    """Alg. "Mixed-precision HODLR Format" with one format at every level."""
+    case = Case("c2_s", n=4096, depth=4, eps=1e-3)
+    h = case.library_op()
+    h.set_level_precisions([fmt] * case.depth, H.ACC_FP32)
+    for b in (0, h.nblocks - 1):
+        uc, ue, vc, ve = h.export_block(b, from_device=True)
+        qu = Q.quantize(case.op.U[b], fmt)
+        assert np.array_equal(uc, qu.codes) and np.array_equal(ue, qu.exps)
+    for nrhs in (1, 4):
+        _run(case, h, [fmt] * case.depth, nrhs, "fp32", "fp32", f"forced-{fmt}")
+
+
+def test_mixed_formats_and_fp64_accumulation():
+    case = Case("c2_s", n=4096, depth=5, eps=1e-3)
+    fm = ["fp64", "fp32", "bf16", "fp16", "e4m3"]
+    h = case.library_op()
+    h.set_level_precisions(fm, H.ACC_FP64)
+    assert h.info()["acc_dtype"] == "fp64"
+    _run(case, h, fm, 3, "fp32", "fp64", "mixed-acc64")
+    h.set_level_precisions(["e5m2", "fp16", "bf16", "fp32", "fp64"])
+    _run(case, h, ["e5m2", "fp16", "bf16", "fp32", "fp64"], 2, "fp64", "fp32", "mixed-xy64")
+
+
+@pytest.mark.parametrize("cfg", ["mat1", "mat2", "mat3", "mat4"])
+def test_paper_kernels_padded_leaves(cfg):
+    """n = 2000, depth 8: leaves of 7-8 rows, padded to 16 on the device."""
+    case = Case(cfg)
+    h = case.library_op()
+    h.assign_precision(case.eps, case.cfg.allowed, case.norms2)
+    a = case.oracle_assign(case.cfg.allowed)
+    assert [lv[0] for lv in h.levels()] == a.fmt
+    X, yg, _, _ = _run(case, h, a.fmt, 2, "fp64", h.info()["acc_dtype"], cfg)
+    A = case.cfg.kernel.dense(case.P)
+    nA = np.sqrt(case.op.norm2_all)
+    for j in range(2):
+        eta = np.linalg.norm(yg[:, j] - A @ X[:, j]) / (nA * np.linalg.norm(X[:, j]))
+        assert eta <= BD.matvec_backward_bound(case.depth, case.eps)
+
+
+def test_edge_cases_depth0_n1_rank0_empty_leaves():
+    # depth 0: a single dense leaf
+    rng = np.random.default_rng(3)
+    D = rng.standard_normal((37, 37))
+    h = H.Operator(37, 0, [D], [], [])
+    X = rng.standard_normal((37, 2))
+    yg = _gpu_product(h, X, "fp64")
+    assert np.allclose(yg, D @ X, rtol=0, atol=1e-13 * np.abs(D).sum())
+    # n = 1
+    h1 = H.Operator(1, 0, [np.array([[2.5]])], [], [])
+    assert _gpu_product(h1, np.array([[4.0]]), "fp64")[0, 0] == 10.0
+    # rank-0 blocks everywhere, ragged leaves
+    case = Case("c2_s", n=999, depth=3, eps=0.99)
+    h2 = case.library_op()
+    h2.set_level_precisions(["fp32"] * 3)
+    _run(case, h2, ["fp32"] * 3, 1, "fp32", "fp32", "eps0.99")
+    # empty leaves (given leaf bounds)
+    case3 = Case("c2_s", n=600, depth=2, eps=1e-4, leaf_bounds=[0, 0, 250, 250, 600])
+    h3 = case3.library_op()
+    h3.set_level_precisions(["fp32", "fp16"])
+    _run(case3, h3, ["fp32", "fp16"], 3, "fp32", "fp32", "empty-leaves")
+
+
+def test_deterministic_and_stream_safe():
+    case = Case("c2_s", n=4096, depth=4, eps=1e-5)
+    h = case.library_op()
+    h.assign_precision(case.eps, case.cfg.allowed, case.norms2)
+    X = case.cfg.X(4)[:4096]
+    Xd = H.colmajor_empty(4096, 4, torch.float32, DEV)
+    Xd.copy_(torch.from_numpy(np.asfortranarray(X)).float())
+    y1 = h.matvec(Xd).clone()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        y2 = h.matvec(Xd, stream=s)
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+
+
+@pytest.mark.slow
+def test_c2_full_size_bench_workload():
+    """The benchmarked workload at full size (n = 65536, depth 8)."""
+    case = Case("c2")
+    h = case.library_op()
+    h.assign_precision(case.eps, case.cfg.allowed, case.norms2)
+    a = case.oracle_assign(case.cfg.allowed)
+    assert [lv[0] for lv in h.levels()] == a.fmt
+    for nrhs in (1, 32):
+        _run(case, h, a.fmt, nrhs, "fp32", "fp32", "c2-full")
