@@ -1,0 +1,268 @@
+"""Benchmark of the mixed-precision HODLR matrix-vector product on one GPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--nrhs 1] [--workload c2]
+
+A step is one full product Y = A_H X (contraction, reduction, expansion and
+leaves) over one batch of right-hand sides, with the operator and X already
+resident in HBM.  The default workload is the 65536-point 2D Gaussian-kernel
+operator (Morton order, leaf 256, depth 8, eps = 1e-6, formats chosen by the
+adaptive rule from fp32/bf16/fp16) with one fp32 right-hand side.  Printed
+as one JSON line:
+
+* value: algorithmic GB/s = B_alg / time per step, where
+  B_alg = 8 sum m_i^2 + sum_b (r_b + c_b) p_b s(f_b) + scaled columns
+          + n nrhs (s_X + s_Y)
+  (leaves, factor codes, scales, X read once, Y written once);
+* gflops: F_alg / time, F_alg = 2 nrhs (sum m_i^2 + sum_b (r_b + c_b) p_b);
+* roofline: the dominant kernel (expansion + leaves: leaf blocks, U codes,
+  X and Y), its algorithmic bytes per launch over its mean duration from HIP
+  events recorded around it on its stream during the timed steps;
+* speedup_vs_fp64: same operator with every level stored in fp64 and fp64
+  accumulation (the uniform-precision product on the same GPU);
+* cpu_baseline: the CPU oracle's fp64 product of the same stored operator
+  on the host's cores, over a bounded number of repetitions.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_expand_c2.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2407_21637_amd", "csrc", "kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def build_operator(cfg, H):
+    """Compress the workload over the library's partition (host, untimed)."""
+    from hodlr_inputs.compress import compress
+    desc = H.tree_blocks(cfg.n, cfg.depth)
+    lb = H.tree_bounds(cfg.n, cfg.depth)[cfg.depth]
+    leaves = [(int(lb[i]), int(lb[i + 1] - lb[i])) for i in range(len(lb) - 1)]
+    blocks = [(int(r0), int(nr), int(c0), int(nc)) for _, r0, nr, c0, nc in desc]
+    P = cfg.points()
+    t = time.time()
+    op = compress(cfg.kernel, P, blocks, leaves, cfg.eps, cfg.rule)
+    log(f"[bench] compressed {cfg.name}: n={cfg.n} depth={cfg.depth} in {time.time() - t:.1f}s")
+    return P, blocks, leaves, op
+
+
+def work(h, n, nrhs, xy_bytes):
+    inf = h.info()
+    B = inf["leaf_bytes"] + inf["factor_bytes"] + inf["scale_bytes"] + n * nrhs * 2 * xy_bytes
+    lr = 0
+    ubytes = 0
+    for b in range(h.nblocks):
+        bi = h.block(b)
+        s = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2, "e4m3": 1, "e5m2": 1}[bi["dtype"]]
+        lr += (bi["nrows"] + bi["ncols"]) * bi["rank"]
+        ubytes += bi["nrows"] * bi["rank"] * s
+    F = 2 * nrhs * (inf["leaf_bytes"] // 8 + lr)
+    expand_bytes = inf["leaf_bytes"] + ubytes + n * nrhs * 2 * xy_bytes
+    return B, F, expand_bytes
+
+
+def time_steps(h, X, Y, steps, warmup, torch, profile=True):
+    for _ in range(warmup):
+        h.matvec(X, Y)
+    torch.cuda.synchronize()
+    if profile:
+        h.profile(steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        h.matvec(X, Y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    phases = h.profile_read() if profile else None
+    if profile:
+        h.profile(0)
+    return ms, phases
+
+
+def time_cold(h, X, Y, reps, torch):
+    """Per-product time with the caches flushed (1 GiB written) before each."""
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=X.device)
+    out = []
+    for _ in range(reps):
+        flush.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        h.matvec(X, Y)
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    del flush
+    return float(np.median(out))
+
+
+def cpu_baseline(cfg, blocks, leaves, op, level_fmt, B_alg, X, budget_s=12.0):
+    """The oracle's product of the same stored operator, timed on the host."""
+    from oracle import matvec as MV
+    from oracle import quantize as Q
+    from oracle import tree as T
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    oblocks = T.blocks(cfg.n, cfg.depth)
+    U = [Q.quantize(u, level_fmt[b.level - 1]).values for b, u in zip(oblocks, op.U)]
+    V = [Q.quantize(v, level_fmt[b.level - 1]).values for b, v in zip(oblocks, op.V)]
+    lb = T.leaves(cfg.n, cfg.depth)
+    MV.matvec(cfg.n, oblocks, lb, op.leaves, U, V, X)        # warm-up
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        y = MV.matvec(cfg.n, oblocks, lb, op.leaves, U, V, X)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    sec = (time.perf_counter() - t0) / reps
+    return {"value": round(B_alg / sec / 1e9, 4), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{reps} full products (n={cfg.n}, nrhs={X.shape[1]}) of the oracle's fp64 HODLR_MATVEC "
+                      f"on the same stored operator, {sec * 1e3:.1f} ms each"}, y, U, V, oblocks, lb
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: the product shards by subtree with a "
+                                   "small exchange of T (see DESIGN.md), which is not implemented; "
+                                   "run with --gpus 1"}), flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_2407_21637_amd as H
+    from hodlr_inputs import configs as CF
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    H.lib()   # fail loudly if the HIP library is not built
+    dev = torch.device("cuda:0")
+    cfg = CF.get(args.workload)
+    P, blocks, leaves, op = build_operator(cfg, H)
+    norms2 = np.concatenate([[op.norm2_all], op.norm2_blocks])
+    t = time.time()
+    h = H.Operator(cfg.n, cfg.depth, op.leaves, op.U, op.V, device=0)
+    h.assign_precision(cfg.eps, cfg.allowed, norms2)
+    fmts = [lv[0] for lv in h.levels()]
+    log(f"[bench] operator on GPU in {time.time() - t:.1f}s; formats {fmts}; acc {h.info()['acc_dtype']}")
+
+    xdt = torch.float32 if cfg.x_dtype == "fp32" else torch.float64
+    xb = 4 if cfg.x_dtype == "fp32" else 8
+    Xh = cfg.X(max(args.nrhs, 32))
+    results = {}
+    for nrhs in sorted({args.nrhs, 32}):
+        X = H.colmajor_empty(cfg.n, nrhs, xdt, dev)
+        X.copy_(torch.from_numpy(np.asfortranarray(Xh[:, :nrhs])).to(xdt))
+        Y = H.colmajor_empty(cfg.n, nrhs, xdt, dev)
+        B, Fl, EB = work(h, cfg.n, nrhs, xb)
+        ms, ph = time_steps(h, X, Y, args.steps, args.warmup, torch)
+        cold = time_cold(h, X, Y, 10, torch)
+        results[nrhs] = dict(ms=ms, phases=ph, B=B, F=Fl, EB=EB, cold_ms=cold, X=X, Y=Y)
+        log(f"[bench] nrhs={nrhs}: {ms * 1e3:.1f} us/step, {B / ms / 1e6:.1f} GB/s, cold {cold * 1e3:.1f} us, "
+            f"phases {ph}")
+
+    # uniform-fp64 product on the same GPU, same ranks
+    h.set_level_precisions(["fp64"] * cfg.depth, H.ACC_FP64)
+    r0 = results[args.nrhs]
+    ms64, _ = time_steps(h, r0["X"], r0["Y"], args.steps, args.warmup, torch, profile=False)
+    B64, _, _ = work(h, cfg.n, args.nrhs, xb)
+    h.assign_precision(cfg.eps, cfg.allowed, norms2)
+    log(f"[bench] uniform fp64: {ms64 * 1e3:.1f} us/step")
+
+    r = results[args.nrhs]
+    ph = r["phases"]["expand"]
+    exp_ms = ph[0] / max(ph[1], 1)
+    achieved = r["EB"] / (exp_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel_sha") == kernel_hash() and tr.get("workload") == cfg.name and \
+                tr.get("nrhs") == args.nrhs:
+            traffic = tr.get("bytes_per_launch")
+    value = r["B"] / (r["ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "HODLR matvec GB/s & Gflop/s (% roofline); speedup mixed vs FP64 at fixed eps",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.description}; n={cfg.n}, leaf {cfg.n >> cfg.depth}, "
+                               f"depth {cfg.depth}, eps={cfg.eps:g}, formats {fmts}, fp32 X nrhs={args.nrhs}",
+                   "n": cfg.n, "depth": cfg.depth, "eps": cfg.eps, "nrhs": args.nrhs, "formats": fmts,
+                   "accumulation": h.info()["acc_dtype"]},
+        "gflops": round(r["F"] / (r["ms"] * 1e-3) / 1e9, 2),
+        "hbm_frac": round(value / HBM_PEAK_GBS, 4),
+        "alg_bytes": int(r["B"]),
+        "alg_flops": int(r["F"]),
+        "cold_cache_gbs": round(r["B"] / (r["cold_ms"] * 1e-3) / 1e9, 2),
+        "speedup_vs_fp64": round(ms64 / r["ms"], 3),
+        "fp64_gbs": round(B64 / (ms64 * 1e-3) / 1e9, 2),
+        "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in r["phases"].items() if v[1]},
+        "roofline": {"bound": "hbm", "kernel": "k_expand (expansion + fp64 leaves)",
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "alg_bytes_per_launch": int(r["EB"]), "mean_launch_us": round(exp_ms * 1e3, 2)},
+    }
+    if 32 in results and args.nrhs != 32:
+        r32 = results[32]
+        out["nrhs32"] = {"gbs": round(r32["B"] / (r32["ms"] * 1e-3) / 1e9, 2),
+                         "gflops": round(r32["F"] / (r32["ms"] * 1e-3) / 1e9, 2),
+                         "ms_per_step": round(r32["ms"], 5)}
+    if not args.no_cpu:
+        Xc = Xh[:, :args.nrhs]
+        cb, y_ora, U, V, oblocks, lb = cpu_baseline(cfg, blocks, leaves, op, fmts, r["B"], Xc)
+        out["cpu_baseline"] = cb
+        # accuracy of the timed product against the oracle
+        from oracle import bounds as BD
+        from oracle import matvec as MV
+        h.matvec(r["X"], r["Y"])
+        torch.cuda.synchronize()
+        yg = r["Y"].cpu().double().numpy()
+        z = MV.matvec_abs(cfg.n, oblocks, lb, op.leaves, U, V, Xc)
+        M = BD.chain_length(oblocks, op.ranks, [m for _, m in lb], cfg.depth)
+        u_acc = 2.0 ** -24 if h.info()["acc_dtype"] == "fp32" else 2.0 ** -53
+        tau = BD.tolerance_prob(z, y_ora, M, u_acc, 2.0 ** -24 if xb == 4 else 2.0 ** -53)
+        err = np.abs(yg - y_ora)
+        out["check"] = {"max_err_over_tau_prob": float((err / tau).max()),
+                        "rel_err_vs_oracle": float(np.linalg.norm(err) / np.linalg.norm(y_ora))}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
