@@ -14,9 +14,9 @@ as one JSON line:
           + n nrhs (s_X + s_Y)
   (leaves, factor codes, scales, X read once, Y written once);
 * gflops: F_alg / time, F_alg = 2 nrhs (sum m_i^2 + sum_b (r_b + c_b) p_b);
-* roofline: the dominant kernel (expansion + leaves: leaf blocks, U codes,
-  X and Y), its algorithmic bytes per launch over its mean duration from HIP
-  events recorded around it on its stream during the timed steps;
+* roofline: the product is one fused kernel; its algorithmic bytes per
+  launch (B_alg) over its mean duration from HIP events recorded around it
+  on its stream during the timed steps;
 * speedup_vs_fp64: same operator with every level stored in fp64 and fp64
   accumulation (the uniform-precision product on the same GPU);
 * cpu_baseline: the CPU oracle's fp64 product of the same stored operator
@@ -39,7 +39,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_expand_c2.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matvec_c2.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2407_21637_amd", "csrc", "kernels.hip")
 
 
@@ -69,15 +69,11 @@ def work(h, n, nrhs, xy_bytes):
     inf = h.info()
     B = inf["leaf_bytes"] + inf["factor_bytes"] + inf["scale_bytes"] + n * nrhs * 2 * xy_bytes
     lr = 0
-    ubytes = 0
     for b in range(h.nblocks):
         bi = h.block(b)
-        s = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2, "e4m3": 1, "e5m2": 1}[bi["dtype"]]
         lr += (bi["nrows"] + bi["ncols"]) * bi["rank"]
-        ubytes += bi["nrows"] * bi["rank"] * s
     F = 2 * nrhs * (inf["leaf_bytes"] // 8 + lr)
-    expand_bytes = inf["leaf_bytes"] + ubytes + n * nrhs * 2 * xy_bytes
-    return B, F, expand_bytes
+    return B, F, B
 
 
 def time_steps(h, X, Y, steps, warmup, torch, profile=True):
@@ -199,7 +195,7 @@ def main():
     log(f"[bench] uniform fp64: {ms64 * 1e3:.1f} us/step")
 
     r = results[args.nrhs]
-    ph = r["phases"]["expand"]
+    ph = r["phases"]["matvec"]
     exp_ms = ph[0] / max(ph[1], 1)
     achieved = r["EB"] / (exp_ms * 1e-3) / 1e9
     traffic = None
@@ -234,7 +230,7 @@ def main():
         "speedup_vs_fp64": round(ms64 / r["ms"], 3),
         "fp64_gbs": round(B64 / (ms64 * 1e-3) / 1e9, 2),
         "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in r["phases"].items() if v[1]},
-        "roofline": {"bound": "hbm", "kernel": "k_expand (expansion + fp64 leaves)",
+        "roofline": {"bound": "hbm", "kernel": "k_matvec (fused product)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_launch": int(r["EB"]), "mean_launch_us": round(exp_ms * 1e3, 2)},

@@ -22,6 +22,7 @@
 //    in a fixed order (deterministic).
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 
 namespace hodlr {
@@ -30,6 +31,10 @@ enum Fmt : int32_t { F64 = 0, F32 = 1, BF16 = 2, F16 = 3, E4M3 = 4, E5M2 = 5, NF
 
 constexpr int kRowAlign = 16;        // padded rows per leaf are a multiple of this
 constexpr int kPanelAlign = 256;     // byte alignment of every panel
+constexpr int kTileRows = 128;       // padded rows of an expansion tile
+constexpr int kItemRowsMax = 4096;   // rows of a contraction item (4 waves x 4 slabs x 256)
+constexpr int kMaxDepth = 24;
+constexpr size_t kMaxLds = 65536;    // dynamic LDS per workgroup
 
 inline int fmt_bytes(int f) {
     return f == F64 ? 8 : f == F32 ? 4 : (f == BF16 || f == F16) ? 2 : 1;
@@ -88,7 +93,10 @@ struct KParams {
     double* partial;             // workspace: sum over items of rank * nrhs
     double* T;                   // workspace: sum over blocks of rank * nrhs
     void* xpad;                  // workspace: padded copy of X (npad * nrhs), if needed
+    int32_t* sync;               // workspace: 4 + 2 * nblocks counters, zero between launches
     int64_t npad;                // padded rows
+    int32_t max_leaf;            // largest leaf (rows)
+    int32_t max_rank_path;       // largest sum of ranks over the blocks of one leaf's ancestors
     int32_t depth;
     int32_t nblocks;
     int32_t nleaves;
@@ -97,7 +105,7 @@ struct KParams {
     int32_t padded;              // 1 if any leaf has padding rows (X goes through xpad)
 };
 
-constexpr int kPhases = 4;     // padded X copy, contraction, reduction, expansion
+constexpr int kPhases = 4;     // padded X copy, fused product, (reserved), (reserved)
 
 // Launch the whole product on `stream`.  xy_double: X/Y are fp64 (else fp32);
 // acc_double: accumulation precision of Y.  events: NULL, or 2 * kPhases

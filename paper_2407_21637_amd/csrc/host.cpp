@@ -221,7 +221,8 @@ struct Workspace {
     double* partial = nullptr;
     double* T = nullptr;
     void* xpad = nullptr;
-    int64_t cap_partial = 0, cap_T = 0, cap_xpad = 0;
+    int32_t* sync = nullptr;   // counters of the fused launch; zeroed once, self-resetting
+    int64_t cap_partial = 0, cap_T = 0, cap_xpad = 0, cap_sync = 0;
 };
 
 struct hodlr_op_s {
@@ -257,6 +258,8 @@ struct hodlr_op_s {
     int64_t total_item_rank = 0;
     int64_t codes_bytes = 0;   // sum (r+c) p s(f)
     int64_t scaled_cols = 0;
+    int32_t max_leaf = 0;
+    int32_t max_rank_path = 0;
 
     // device
     int device = -1;
@@ -325,6 +328,7 @@ void free_device(hodlr_op_s* op) {
         dev_free(kv.second.partial);
         dev_free(kv.second.T);
         dev_free(kv.second.xpad);
+        dev_free(kv.second.sync);
     }
     op->ws.clear();
 }
@@ -350,13 +354,13 @@ hodlr_status upload(T** dst, const T* src, size_t count, const char* what) {
     return HODLR_OK;
 }
 
-// Chunk rows of a contraction work item: aim at ~64 KB of codes per item,
-// in multiples of 256 rows (one wave of 64 lanes x 4 rows).
+// Rows of a contraction work item: a multiple of 1024 (four waves, one
+// 256-row slab each) aiming at ~256 KB of codes, at most kItemRowsMax.
 int32_t item_rows(int rank, int f) {
     const int64_t per_row = int64_t(rank) * fmt_bytes(f);
-    int64_t g = per_row > 0 ? (64 * 1024) / (256 * per_row) : 16;
-    g = std::max<int64_t>(1, std::min<int64_t>(16, g));
-    return int32_t(256 * g);
+    int64_t g = per_row > 0 ? (256 * 1024) / (1024 * per_row) : 4;
+    g = std::max<int64_t>(1, std::min<int64_t>(kItemRowsMax / 1024, g));
+    return int32_t(1024 * g);
 }
 
 // Quantise block b's factor F (rows x p, fp64, ld = rows) in format f;
@@ -470,6 +474,12 @@ hodlr_status pack(hodlr_op_s* op) {
     op->fac_bytes = std::max<int64_t>(off, kPanelAlign);
     op->total_rank = toff;
     op->total_item_rank = poff;
+    op->max_rank_path = 0;
+    for (int i = 0; i < op->nleaves; ++i) {
+        int32_t sum = 0;
+        for (int k = 1; k <= op->depth; ++k) sum += op->rank[((1 << k) - 2) + (i >> (op->depth - k))];
+        op->max_rank_path = std::max(op->max_rank_path, sum);
+    }
 
     std::vector<uint8_t> img;
     try {
@@ -549,6 +559,8 @@ hodlr_status pack_leaves(hodlr_op_s* op) {
         pr += op->lmp[i];
     }
     op->npad = pr;
+    op->max_leaf = 0;
+    for (int i = 0; i < nl; ++i) op->max_leaf = std::max<int32_t>(op->max_leaf, int32_t(lb[i + 1] - lb[i]));
     if (op->npad >= (int64_t(1) << 31))
         return fail(HODLR_E_UNSUPPORTED, "padded size %lld exceeds 2^31 rows", (long long)pr);
     op->ldesc.assign(nl, LeafDesc{});
@@ -562,11 +574,11 @@ hodlr_status pack_leaves(hodlr_op_s* op) {
         L.mp = int32_t(op->lmp[i]);
         L.prow0 = int32_t(op->lprow0[i]);
         doff += int64_t(L.mp) * L.mp;
-        for (int32_t r = 0; r < L.mp; r += 256) {
+        for (int32_t r = 0; r < L.mp; r += kTileRows) {
             ETile t{};
             t.leaf = i;
             t.r0 = r;
-            t.nr = std::min<int32_t>(256, L.mp - r);
+            t.nr = std::min<int32_t>(kTileRows, L.mp - r);
             op->etiles.push_back(t);
         }
     }
@@ -958,6 +970,13 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
         return r;
     if ((r = grow(reinterpret_cast<void**>(&w.T), &w.cap_T, need_t * 8, "T")) != HODLR_OK) return r;
     if (need_x && (r = grow(&w.xpad, &w.cap_xpad, need_x, "padded X")) != HODLR_OK) return r;
+    const int64_t need_s = int64_t(4 + 2 * op->nb) * 4;
+    if (need_s > w.cap_sync) {
+        if ((r = grow(reinterpret_cast<void**>(&w.sync), &w.cap_sync, need_s, "counters")) != HODLR_OK) return r;
+        hipError_t e = hipMemset(w.sync, 0, size_t(need_s));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "clearing counters");
+    }
     kp->fac = op->d_fac;
     kp->leafd = op->d_leaf;
     kp->blocks = op->d_blocks;
@@ -968,7 +987,10 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
     kp->partial = w.partial;
     kp->T = w.T;
     kp->xpad = w.xpad;
+    kp->sync = w.sync;
     kp->npad = op->npad;
+    kp->max_leaf = op->max_leaf;
+    kp->max_rank_path = op->max_rank_path;
     kp->depth = op->depth;
     kp->nblocks = op->nb;
     kp->nleaves = op->nleaves;
@@ -1005,6 +1027,9 @@ hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int6
     }
     const int he = launch_matvec(kp, X, ldx, Y, ldy, nrhs, xy_dtype == HODLR_FP64, op->acc_double, stream,
                                  ev, ran);
+    if (he == int(hipErrorInvalidConfiguration))
+        return fail(HODLR_E_UNSUPPORTED, "leaf size %d with path rank %d needs more than 64 KB of LDS",
+                    op->max_leaf, op->max_rank_path);
     if (slot >= 0)
         for (int ph = 0; ph < kPhases; ++ph) op->prof_ran[size_t(slot) * kPhases + ph] = ran[ph] ? 1 : 0;
     if (he != 0) return fail(HODLR_E_DEVICE, "kernel launch: %s", hipGetErrorString(hipError_t(he)));
