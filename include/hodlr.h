@@ -196,7 +196,8 @@ hodlr_status hodlr_matvec_batched(const hodlr_op* ops, int32_t count, const void
  * of this handle record a HIP event pair around each of their kernel phases
  * on the launch stream (0 turns recording off and drops the records).
  * Phases: 0 padded copy of X (only when a leaf size is not a multiple of
- * 16), 1 the product kernel, 2 and 3 reserved (never recorded).  hodlr_profile_read synchronises on the recorded
+ * 16), 1 contraction (T = V^T X for every block), 2 expansion and leaves
+ * (Y = D X + U T), 3 reserved (never recorded).  hodlr_profile_read synchronises on the recorded
  * events and returns, per phase, the summed duration in milliseconds and
  * the number of launches timed; it then clears the records. */
 hodlr_status hodlr_profile(hodlr_op op, int32_t capacity);

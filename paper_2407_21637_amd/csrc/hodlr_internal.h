@@ -9,11 +9,16 @@
 // one contiguous padded range.  Padding rows hold zeros in every factor
 // panel and in the leaf blocks.
 //
-//  * leaves: fp64, leaf i column-major mp_i x mp_i at element offset d_off.
+//  * leaves: fp64, leaf i (mp_i x mp_i) at element offset d_off, cut at its
+//    expansion tiles: tile rows [r0, r0+nr) are column-major (ld = nr) at
+//    d_off + r0 * mp_i.
 //  * factor panels: for block b (rows = node j of level k, columns = node
 //    j^1), the U panel covers the padded rows of node j and the V panel the
-//    padded rows of node j^1; both column-major with ld = padded node rows,
-//    rank_b columns, codes of the level's format, 256-byte aligned.
+//    padded rows of node j^1, rank_b columns, codes of the level's format,
+//    256-byte aligned.  Each panel is cut into row chunks stored
+//    column-major one after another (chunk rows [c0, c0+h) at c0 * rank,
+//    ld = h): U panels at the expansion tiles of the node's leaves, V panels
+//    at the contraction items.  Every work item reads one contiguous chunk.
 //  * tscale_b[j] = 2^-(eV_j + eU_j) times the decode compensation of the
 //    format (fp8 e4m3 decodes through fp16 at 2^-8 of its value, once per
 //    factor), applied once to T_b = V_b^T X.
@@ -29,10 +34,21 @@ namespace hodlr {
 
 enum Fmt : int32_t { F64 = 0, F32 = 1, BF16 = 2, F16 = 3, E4M3 = 4, E5M2 = 5, NFMT = 6 };
 
+// Tuning parameters (compile-time; the build may override them).
+#ifndef HODLR_TILE_ROWS
+#define HODLR_TILE_ROWS 128          // padded rows of an expansion tile (64, 128 or 256)
+#endif
+#ifndef HODLR_ITEM_KB
+#define HODLR_ITEM_KB 256            // target KB of codes per contraction item
+#endif
+#ifndef HODLR_ITEM_MIN_ROWS
+#define HODLR_ITEM_MIN_ROWS 1024     // smallest contraction item (multiple of 256)
+#endif
+
 constexpr int kRowAlign = 16;        // padded rows per leaf are a multiple of this
 constexpr int kPanelAlign = 256;     // byte alignment of every panel
-constexpr int kTileRows = 128;       // padded rows of an expansion tile
-constexpr int kItemRowsMax = 4096;   // rows of a contraction item (4 waves x 4 slabs x 256)
+constexpr int kTileRows = HODLR_TILE_ROWS;
+constexpr int kItemRowsMax = 4096;   // rows of a contraction item (at most 16 slabs of 256)
 constexpr int kMaxDepth = 24;
 constexpr size_t kMaxLds = 65536;    // dynamic LDS per workgroup
 
@@ -54,7 +70,7 @@ struct BlockDesc {        // one per off-diagonal block, canonical order
     int32_t vrows;        // padded rows of the column node (= V panel ld)
     int32_t item0;        // first contraction item of this block
     int32_t nitems;       // number of contraction items
-    int32_t pad_;
+    int32_t pad_;         // rows of a contraction item (V panel chunk)
 };
 
 struct LeafDesc {
@@ -93,10 +109,11 @@ struct KParams {
     double* partial;             // workspace: sum over items of rank * nrhs
     double* T;                   // workspace: sum over blocks of rank * nrhs
     void* xpad;                  // workspace: padded copy of X (npad * nrhs), if needed
-    int32_t* sync;               // workspace: 4 + 2 * nblocks counters, zero between launches
+    int32_t* sync;               // workspace: sync_words(nblocks) counters, zero between launches
     int64_t npad;                // padded rows
     int32_t max_leaf;            // largest leaf (rows)
     int32_t max_rank_path;       // largest sum of ranks over the blocks of one leaf's ancestors
+    int32_t max_items_rank;      // largest nitems * rank of a block (partials to add up)
     int32_t depth;
     int32_t nblocks;
     int32_t nleaves;
@@ -105,7 +122,12 @@ struct KParams {
     int32_t padded;              // 1 if any leaf has padding rows (X goes through xpad)
 };
 
-constexpr int kPhases = 4;     // padded X copy, fused product, (reserved), (reserved)
+// Counters of the contraction launch: kSyncHead reserved words, then one
+// arrival counter per block (zero between launches).
+constexpr int kSyncHead = 4;
+constexpr int64_t sync_words(int64_t nblocks) { return kSyncHead + nblocks; }
+
+constexpr int kPhases = 4;     // padded X copy, contraction, expansion, (reserved)
 
 // Launch the whole product on `stream`.  xy_double: X/Y are fp64 (else fp32);
 // acc_double: accumulation precision of Y.  events: NULL, or 2 * kPhases

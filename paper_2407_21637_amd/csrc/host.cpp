@@ -260,6 +260,7 @@ struct hodlr_op_s {
     int64_t scaled_cols = 0;
     int32_t max_leaf = 0;
     int32_t max_rank_path = 0;
+    int32_t max_items_rank = 0;
 
     // device
     int device = -1;
@@ -354,13 +355,14 @@ hodlr_status upload(T** dst, const T* src, size_t count, const char* what) {
     return HODLR_OK;
 }
 
-// Rows of a contraction work item: a multiple of 1024 (four waves, one
-// 256-row slab each) aiming at ~256 KB of codes, at most kItemRowsMax.
+// Rows of a contraction work item: a multiple of 256 (one slab of 64 lanes
+// x 4 rows), at least HODLR_ITEM_MIN_ROWS, aiming at HODLR_ITEM_KB of codes,
+// at most kItemRowsMax.
 int32_t item_rows(int rank, int f) {
     const int64_t per_row = int64_t(rank) * fmt_bytes(f);
-    int64_t g = per_row > 0 ? (256 * 1024) / (1024 * per_row) : 4;
-    g = std::max<int64_t>(1, std::min<int64_t>(kItemRowsMax / 1024, g));
-    return int32_t(1024 * g);
+    int64_t g = per_row > 0 ? (int64_t(HODLR_ITEM_KB) * 1024) / (256 * per_row) : kItemRowsMax / 256;
+    g = std::max<int64_t>(HODLR_ITEM_MIN_ROWS / 256, std::min<int64_t>(kItemRowsMax / 256, g));
+    return int32_t(256 * g);
 }
 
 // Quantise block b's factor F (rows x p, fp64, ld = rows) in format f;
@@ -396,23 +398,50 @@ void put_code(uint8_t* dst, int f, uint64_t code) {
     }
 }
 
-// Padded row (relative to the node start) of unpadded row r (relative to the
-// node's first index) for node j of level k.
-struct RowMap {
-    std::vector<int64_t> pr;   // padded offset of every row of the node
+// Where row r (unpadded, relative to the node's first index) of a factor
+// panel lives.  A panel of node j at level k is cut into row chunks and each
+// chunk is stored column-major on its own (chunk-contiguous layout), so that
+// every work item streams one contiguous piece: U panels are cut at the
+// expansion tiles of the node's leaves, V panels at the contraction items
+// (every item_rows rows).  Element (r, col) of a rank-p panel is at
+// chunk_start * p + col * chunk_rows + row_in_chunk.
+struct RowLoc {
+    int64_t cs;     // chunk start (padded rows, node-relative)
+    int32_t ch;     // chunk rows
+    int32_t in;     // row within the chunk
 };
 
-void node_rowmap(const hodlr_op_s* op, int k, int64_t j, std::vector<int64_t>& out) {
+int64_t loc_index(const RowLoc& L, int64_t col, int64_t p) { return L.cs * p + col * L.ch + L.in; }
+
+// chunk_rows = 0: chunks are the expansion tiles; else fixed chunks of that
+// many rows (the last one shorter).
+void node_rowlocs(const hodlr_op_s* op, int k, int64_t j, int64_t chunk_rows, std::vector<RowLoc>& out) {
     int64_t b, e;
     node_of(op, k, j, &b, &e);
     out.resize(size_t(e - b));
     const int64_t step = int64_t(1) << (op->depth - k);
     const int64_t p0 = op->lprow0[j * step];
+    const int64_t l1 = (j + 1) * step;
+    const int64_t rows = op->lprow0[l1 - 1] + op->lmp[l1 - 1] - p0;
     const int64_t* lb = op->bounds.data() + ((int64_t(1) << op->depth) - 1) + op->depth;
     int64_t idx = 0;
-    for (int64_t l = j * step; l < (j + 1) * step; ++l) {
+    for (int64_t l = j * step; l < l1; ++l) {
         const int64_t m = lb[l + 1] - lb[l];
-        for (int64_t r = 0; r < m; ++r) out[size_t(idx++)] = op->lprow0[l] - p0 + r;
+        const int64_t lrel = op->lprow0[l] - p0;
+        for (int64_t r = 0; r < m; ++r) {
+            RowLoc L;
+            const int64_t pr = lrel + r;
+            if (chunk_rows == 0) {
+                const int64_t t0 = (r / kTileRows) * kTileRows;
+                L.cs = lrel + t0;
+                L.ch = int32_t(std::min<int64_t>(kTileRows, op->lmp[l] - t0));
+            } else {
+                L.cs = (pr / chunk_rows) * chunk_rows;
+                L.ch = int32_t(std::min<int64_t>(chunk_rows, rows - L.cs));
+            }
+            L.in = int32_t(pr - L.cs);
+            out[size_t(idx++)] = L;
+        }
     }
 }
 
@@ -455,8 +484,9 @@ hodlr_status pack(hodlr_op_s* op) {
         ts_off[b] = ts_total;
         ts_total += p;
         d.item0 = int32_t(op->citems.size());
+        d.pad_ = p > 0 ? item_rows(p, f) : 0;     // V chunk rows (contraction item rows)
         if (p > 0) {
-            const int32_t ch = item_rows(p, f);
+            const int32_t ch = d.pad_;
             for (int64_t r = 0; r < vpr; r += ch) {
                 CItem it{};
                 it.block = b;
@@ -474,6 +504,9 @@ hodlr_status pack(hodlr_op_s* op) {
     op->fac_bytes = std::max<int64_t>(off, kPanelAlign);
     op->total_rank = toff;
     op->total_item_rank = poff;
+    op->max_items_rank = 0;
+    for (int b = 0; b < nb; ++b)
+        op->max_items_rank = std::max(op->max_items_rank, op->bdesc[b].nitems * op->bdesc[b].rank);
     op->max_rank_path = 0;
     for (int i = 0; i < op->nleaves; ++i) {
         int32_t sum = 0;
@@ -499,20 +532,20 @@ hodlr_status pack(hodlr_op_s* op) {
         const int64_t j = b - ((int64_t(1) << k) - 2);
         const int f = d.fmt;
         const int s = fmt_bytes(f);
-        std::vector<int64_t> umap, vmap;
-        node_rowmap(op, k, j, umap);
-        node_rowmap(op, k, j ^ 1, vmap);
+        std::vector<RowLoc> umap, vmap;
+        node_rowlocs(op, k, j, 0, umap);
+        node_rowlocs(op, k, j ^ 1, d.pad_, vmap);
         std::vector<int32_t> eu(p), ev(p);
         uint8_t* ub = img.data() + d.u_off;
         uint8_t* vb = img.data() + d.v_off;
         hodlr_status r = quantize_factor(op->U[b], hb.nrows, p, f, op->scale_cols, eu.data(),
                                          [&](int64_t i, int jj, uint64_t c) {
-                                             put_code(ub + (int64_t(jj) * d.urows + umap[i]) * s, f, c);
+                                             put_code(ub + loc_index(umap[i], jj, p) * s, f, c);
                                          });
         if (r == HODLR_OK)
             r = quantize_factor(op->V[b], hb.ncols, p, f, op->scale_cols, ev.data(),
                                 [&](int64_t i, int jj, uint64_t c) {
-                                    put_code(vb + (int64_t(jj) * d.vrows + vmap[i]) * s, f, c);
+                                    put_code(vb + loc_index(vmap[i], jj, p) * s, f, c);
                                 });
         if (r != HODLR_OK) {
             st[b] = r;
@@ -589,11 +622,17 @@ hodlr_status pack_leaves(hodlr_op_s* op) {
     } catch (const std::bad_alloc&) {
         return fail(HODLR_E_NOMEM, "host staging of leaves");
     }
+    // leaf i is cut at its expansion tiles; tile rows [r0, r0+nr) are stored
+    // column-major (ld = nr) at d_off + r0 * mp
     parallel_for(nl, [&](int64_t i) {
         const LeafDesc& L = op->ldesc[i];
-        for (int64_t c = 0; c < L.m; ++c)
-            std::memcpy(img.data() + L.d_off + c * L.mp, op->D[i].data() + c * L.m,
-                        sizeof(double) * size_t(L.m));
+        for (int64_t r0 = 0; r0 < L.mp; r0 += kTileRows) {
+            const int64_t nr = std::min<int64_t>(kTileRows, L.mp - r0);
+            double* chunk = img.data() + L.d_off + r0 * L.mp;
+            for (int64_t c = 0; c < L.m; ++c)
+                for (int64_t r = r0; r < std::min<int64_t>(r0 + nr, L.m); ++r)
+                    chunk[c * nr + (r - r0)] = op->D[i][size_t(c * L.m + r)];
+        }
     });
     hipError_t e = hipSetDevice(op->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -896,9 +935,9 @@ hodlr_status hodlr_export_block(hodlr_op op, int32_t block, void* u_codes, int8_
     const int k = hb.level;
     const int64_t j = block - ((int64_t(1) << k) - 2);
     std::vector<int32_t> eu(p), ev(p);
-    std::vector<int64_t> umap, vmap;
-    node_rowmap(op, k, j, umap);
-    node_rowmap(op, k, j ^ 1, vmap);
+    std::vector<RowLoc> umap, vmap;
+    node_rowlocs(op, k, j, 0, umap);
+    node_rowlocs(op, k, j ^ 1, d.pad_, vmap);
     auto put_u = [&](int64_t i, int jj, uint64_t c) {
         if (u_codes) put_code(static_cast<uint8_t*>(u_codes) + (int64_t(jj) * hb.nrows + i) * s, f, c);
     };
@@ -923,11 +962,11 @@ hodlr_status hodlr_export_block(hodlr_op op, int32_t block, void* u_codes, int8_
             if (u_codes)
                 for (int64_t i = 0; i < hb.nrows; ++i)
                     std::memcpy(static_cast<uint8_t*>(u_codes) + (int64_t(jj) * hb.nrows + i) * s,
-                                ub.data() + (int64_t(jj) * d.urows + umap[i]) * s, s);
+                                ub.data() + loc_index(umap[i], jj, p) * s, s);
             if (v_codes)
                 for (int64_t i = 0; i < hb.ncols; ++i)
                     std::memcpy(static_cast<uint8_t*>(v_codes) + (int64_t(jj) * hb.ncols + i) * s,
-                                vb.data() + (int64_t(jj) * d.vrows + vmap[i]) * s, s);
+                                vb.data() + loc_index(vmap[i], jj, p) * s, s);
         }
     }
     for (int jj = 0; jj < p; ++jj) {
@@ -970,7 +1009,7 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
         return r;
     if ((r = grow(reinterpret_cast<void**>(&w.T), &w.cap_T, need_t * 8, "T")) != HODLR_OK) return r;
     if (need_x && (r = grow(&w.xpad, &w.cap_xpad, need_x, "padded X")) != HODLR_OK) return r;
-    const int64_t need_s = int64_t(4 + 2 * op->nb) * 4;
+    const int64_t need_s = sync_words(op->nb) * int64_t(sizeof(int32_t));
     if (need_s > w.cap_sync) {
         if ((r = grow(reinterpret_cast<void**>(&w.sync), &w.cap_sync, need_s, "counters")) != HODLR_OK) return r;
         hipError_t e = hipMemset(w.sync, 0, size_t(need_s));
@@ -991,6 +1030,7 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
     kp->npad = op->npad;
     kp->max_leaf = op->max_leaf;
     kp->max_rank_path = op->max_rank_path;
+    kp->max_items_rank = op->max_items_rank;
     kp->depth = op->depth;
     kp->nblocks = op->nb;
     kp->nleaves = op->nleaves;

@@ -5,22 +5,18 @@
 //   b <- 0;  b_rows(b) += U_b (V_b^T x_cols(b)) for every off-diagonal block;
 //   b_i += D_i x_i for every leaf.
 //
-// One launch does the whole product.  Its workgroups take tickets from a
-// counter in launch order, so ticket t is only taken once every smaller
-// ticket belongs to a running or finished workgroup:
+// Two launches per product (one kernel boundary is the only synchronisation
+// between the phases; no work queue, no spin-waits):
 //
-//  * tickets [0, ncitems): contraction items.  Item = rows [r0, r0+nr) of
-//    the V panel of one block; it writes the partial sums of T_b = V_b^T X
-//    over its rows.  The last item of a block to finish (arrival counter)
-//    adds the block's partials in item order, applies the column scales and
-//    publishes T_b through a ready flag (deterministic, no float atomics).
-//  * tickets [ncitems, ncitems+netiles): expansion tiles.  Tile = 64*RPL
-//    padded rows of one leaf.  It first computes D_i X_i in fp64 (needs
-//    only X), then waits for the T_b of its depth ancestors' blocks, adds
-//    U_b T_b for each level, sums its waves' partial rows and writes Y once.
-//    Tiles only wait on contraction items, which hold smaller tickets, so
-//    the wait always ends; it is bounded anyway (a timed-out tile writes NaN).
-//  * The last workgroup to finish resets the counters for the next launch.
+//  * k_contract, one workgroup per contraction item: item = rows [r0, r0+nr)
+//    of the V panel of one block; it stores the partial sums of
+//    T_b = V_b^T X over its rows and counts itself in the block's arrival
+//    counter.  The last item of a block to arrive adds the block's partials
+//    in item order (deterministic, no float atomics), applies the column
+//    scales, stores T_b and clears the counter for the next launch.
+//  * k_expand, one workgroup per expansion tile: tile = 64*RPL padded rows
+//    of one leaf.  It computes D_i X_i in fp64, adds U_b T_b for each of its
+//    depth ancestors' blocks, sums its waves' partial rows and writes Y once.
 //
 // Stored codes are converted in registers (Sect. 3.3: low-precision
 // storage cast to the working precision on the fly).
@@ -203,13 +199,9 @@ __device__ __forceinline__ double wave_sum63(double v) {
 // ---------------------------------------------------------------------------
 // synchronisation words (int32 workspace, zero between launches)
 // ---------------------------------------------------------------------------
-//   sync[0] ticket counter, sync[1] finished workgroups, sync[2] timed-out
-//   waits (sticky), sync[4 + b] arrivals of block b, sync[4 + nb + b] ready.
-constexpr int kSyncHead = 4;
-constexpr int kWaitSpins = 1 << 24;   // ~1 s of s_sleep(2)
+//   sync[kSyncHead + b]: arrivals of block b's contraction items.
 
 __device__ __forceinline__ int* arrivals(const KParams& kp) { return kp.sync + kSyncHead; }
-__device__ __forceinline__ int* ready(const KParams& kp) { return kp.sync + kSyncHead + kp.nblocks; }
 
 // Data shared between workgroups of one launch (partials, T, counters) is
 // written and read with device-coherent accesses (relaxed atomics at agent
@@ -238,170 +230,192 @@ __device__ __forceinline__ void drain_and_sync() {
     __syncthreads();
 }
 
-__device__ bool wait_ready(int* flag) {
-    for (int i = 0; i < kWaitSpins; ++i) {
-        if (ld_coh(flag) != 0) return true;
-        __builtin_amdgcn_s_sleep(2);
-    }
-    return false;
-}
+
 
 constexpr int kWaves = 4;            // waves per workgroup
 constexpr int kThreads = 64 * kWaves;
-constexpr int kContractCols = 8;     // columns a contraction wave keeps in flight
+#ifndef HODLR_U_UNROLL
+#define HODLR_U_UNROLL 8             // U columns in flight per wave in the expansion
+#endif
+#ifndef HODLR_LEAF_UNROLL
+#define HODLR_LEAF_UNROLL 16         // leaf columns in flight per wave
+#endif
+#ifndef HODLR_EXPAND_MINW
+#define HODLR_EXPAND_MINW 2          // k_expand: minimum resident waves per SIMD
+#endif
+#ifndef HODLR_CONTRACT_MINW
+#define HODLR_CONTRACT_MINW 2
+#endif
+constexpr int kUnroll = HODLR_U_UNROLL;
+constexpr int kLeafUnroll = HODLR_LEAF_UNROLL;
 
 // ---------------------------------------------------------------------------
 // contraction item: partial T_b over rows [r0, r0+nr) of the V panel
 // ---------------------------------------------------------------------------
-// Lane l owns rows 4l..4l+3 of a 256-row slab; wave w takes slabs w, w+4, ...
-// (at most 4 each), keeps their x values in registers and accumulates CJ
-// columns at a time (CJ loads in flight per slab), then reduces each column
-// across its lanes (DPP) into LDS; the four waves' sums make the item's
-// partial.
+// Lane l owns rows 4l..4l+3 of every 256-row slab of the item (at most 16
+// slabs).  Wave w owns columns w, w+4, w+8, ...: for each group of CJ of
+// its columns it issues the loads of every slab at once, accumulates per
+// lane, sums across the wave (DPP) and lane 63 stores the column's partial
+// (device-coherent).  No barrier inside the column loop.
 template <int F, typename CT, typename XT, int RG>
 __device__ void contract_item(const KParams& kp, const CItem& it, const BlockDesc& bd,
-                              const XT* __restrict__ X, int64_t ldx, int nrhs, unsigned char* smem) {
-    constexpr int CJ0 = kContractCols * 4 / int(sizeof(CT)) / RG;   // fp64 keeps half as many
-    constexpr int CJ = CJ0 > 1 ? CJ0 : 2;
-    constexpr int GS = 4;
+                              const XT* __restrict__ X, int64_t ldx, int nrhs) {
     constexpr int S = Codec<F>::kBytes;
-    CT* red = reinterpret_cast<CT*>(smem);          // [kWaves][CJ][RG]
+    constexpr int GS = kItemRowsMax / 256;                          // slabs per item
+    constexpr int CJ0 = (sizeof(CT) == 8 ? 8 : 16) / (GS / 4) / RG;   // loads in flight ~ CJ * slabs
+    constexpr int CJ = CJ0 > 1 ? CJ0 : 1;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int p = bd.rank;
-    const uint8_t* Vp = kp.fac + bd.v_off + int64_t(it.r0) * S;
-    const int64_t ld = bd.vrows;
+    const uint8_t* Vp = kp.fac + bd.v_off + int64_t(it.r0) * p * S;   // the item's chunk
+    const int64_t ld = it.nr;
     double* part = kp.partial + it.poff * nrhs;
     const int nslab = (it.nr + 255) >> 8;
     const int64_t xrow0 = int64_t(bd.vrow0) + it.r0;
     for (int rb = 0; rb < nrhs; rb += RG) {
-        for (int j0 = 0; j0 < p; j0 += CJ) {
+        for (int j0 = wave * CJ; j0 < p; j0 += kWaves * CJ) {
             CT acc[CJ][RG];
 #pragma unroll
             for (int c = 0; c < CJ; ++c)
 #pragma unroll
                 for (int rg = 0; rg < RG; ++rg) acc[c][rg] = CT(0);
-#pragma unroll 1
-            for (int q = 0; q < GS; ++q) {
-                const int row = (wave + kWaves * q) * 256 + 4 * lane;
-                if ((wave + kWaves * q) < nslab && row < it.nr) {
-                    CT v[CJ][4];
+            for (int s0 = 0; s0 < nslab; s0 += GS / 4) {            // slab groups of GS/4
+                CT xr[GS / 4][4][RG];
+                CT v[GS / 4][CJ][4];
+#pragma unroll
+                for (int q = 0; q < GS / 4; ++q) {
+                    const int row = (s0 + q) * 256 + 4 * lane;
+                    const bool ok = s0 + q < nslab && row < it.nr;
 #pragma unroll
                     for (int c = 0; c < CJ; ++c) {
-                        if (j0 + c < p)
-                            Codec<F>::template load<4, CT>(Vp + (int64_t(j0 + c) * ld + row) * S, v[c]);
+                        if (ok && j0 + c < p)
+                            Codec<F>::template load<4, CT>(Vp + (int64_t(j0 + c) * ld + row) * S, v[q][c]);
                         else
-                            v[c][0] = v[c][1] = v[c][2] = v[c][3] = CT(0);
+                            v[q][c][0] = v[q][c][1] = v[q][c][2] = v[q][c][3] = CT(0);
                     }
-                    CT xr[4][RG];
 #pragma unroll
                     for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
-                            xr[i][rg] = (rb + rg < nrhs) ? CT(X[xrow0 + row + i + ldx * (rb + rg)]) : CT(0);
+                            xr[q][i][rg] = (ok && row + i < it.nr && rb + rg < nrhs)
+                                               ? CT(X[xrow0 + row + i + ldx * (rb + rg)]) : CT(0);
+                }
+#pragma unroll
+                for (int q = 0; q < GS / 4; ++q)
 #pragma unroll
                     for (int c = 0; c < CJ; ++c)
 #pragma unroll
                         for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
-                            for (int i = 0; i < 4; ++i) acc[c][rg] += v[c][i] * xr[i][rg];
-                }
+                            for (int i = 0; i < 4; ++i) acc[c][rg] += v[q][c][i] * xr[q][i][rg];
             }
 #pragma unroll
             for (int c = 0; c < CJ; ++c)
 #pragma unroll
                 for (int rg = 0; rg < RG; ++rg) {
                     const CT r = wave_sum63(acc[c][rg]);
-                    if (lane == 63) red[(wave * CJ + c) * RG + rg] = r;
+                    if (lane == 63 && j0 + c < p && rb + rg < nrhs)
+                        st_coh(part + int64_t(rb + rg) * p + j0 + c, double(r));
                 }
-            __syncthreads();
-            if (threadIdx.x < CJ * RG) {
-                const int c = threadIdx.x / RG, rg = threadIdx.x % RG;
-                if (j0 + c < p && rb + rg < nrhs) {
-                    CT s = red[c * RG + rg];
-#pragma unroll
-                    for (int w = 1; w < kWaves; ++w) s += red[(w * CJ + c) * RG + rg];
-                    st_coh(part + int64_t(rb + rg) * p + j0 + c, double(s));
-                }
-            }
-            __syncthreads();
         }
-    }
-}
-
-// The last item of block b adds the block's partials in item order.
-template <typename CT>
-__device__ void finish_block(const KParams& kp, const BlockDesc& bd, int nrhs) {
-    const int p = bd.rank;
-    const int64_t total = int64_t(p) * nrhs;
-    const int64_t base = kp.citems[bd.item0].poff * nrhs;
-    for (int64_t idx = threadIdx.x; idx < total; idx += kThreads) {
-        const int j = int(idx % p);
-        CT s = CT(0);
-        int c = 0;
-        for (; c + 4 <= bd.nitems; c += 4) {
-            const double a0 = ld_coh(kp.partial + base + int64_t(c) * total + idx);
-            const double a1 = ld_coh(kp.partial + base + int64_t(c + 1) * total + idx);
-            const double a2 = ld_coh(kp.partial + base + int64_t(c + 2) * total + idx);
-            const double a3 = ld_coh(kp.partial + base + int64_t(c + 3) * total + idx);
-            s += CT(a0);
-            s += CT(a1);
-            s += CT(a2);
-            s += CT(a3);
-        }
-        for (; c < bd.nitems; ++c) s += CT(ld_coh(kp.partial + base + int64_t(c) * total + idx));
-        st_coh(kp.T + bd.t_off * nrhs + idx, double(s) * kp.tscale[bd.ts_off + j]);
     }
 }
 
 template <typename XT, typename AT, int RG>
-__device__ void run_contract(const KParams& kp, int ticket, const XT* __restrict__ X, int64_t ldx, int nrhs,
-                             unsigned char* smem, int* s_flag) {
-    const CItem it = kp.citems[ticket];
-    const BlockDesc bd = kp.blocks[it.block];
+__device__ void run_contract_item(const KParams& kp, const CItem& it, const BlockDesc& bd,
+                                  const XT* __restrict__ X, int64_t ldx, int nrhs) {
     switch (bd.fmt) {
-        case F64: contract_item<F64, double, XT, RG>(kp, it, bd, X, ldx, nrhs, smem); break;
-        case F32: contract_item<F32, AT, XT, RG>(kp, it, bd, X, ldx, nrhs, smem); break;
-        case BF16: contract_item<BF16, AT, XT, RG>(kp, it, bd, X, ldx, nrhs, smem); break;
-        case F16: contract_item<F16, AT, XT, RG>(kp, it, bd, X, ldx, nrhs, smem); break;
-        case E4M3: contract_item<E4M3, AT, XT, RG>(kp, it, bd, X, ldx, nrhs, smem); break;
-        default: contract_item<E5M2, AT, XT, RG>(kp, it, bd, X, ldx, nrhs, smem); break;
+        case F64: contract_item<F64, double, XT, RG>(kp, it, bd, X, ldx, nrhs); break;
+        case F32: contract_item<F32, AT, XT, RG>(kp, it, bd, X, ldx, nrhs); break;
+        case BF16: contract_item<BF16, AT, XT, RG>(kp, it, bd, X, ldx, nrhs); break;
+        case F16: contract_item<F16, AT, XT, RG>(kp, it, bd, X, ldx, nrhs); break;
+        case E4M3: contract_item<E4M3, AT, XT, RG>(kp, it, bd, X, ldx, nrhs); break;
+        default: contract_item<E5M2, AT, XT, RG>(kp, it, bd, X, ldx, nrhs); break;
     }
-    // publish the partial; the last arrival of the block reduces it
+}
+
+// The last item of block b to arrive adds the block's partials in item
+// order: all of them are staged in LDS first (every load in flight), then
+// each output is summed and scaled, and T_b is stored device-coherently.
+template <typename CT>
+__device__ void finish_block(const KParams& kp, const BlockDesc& bd, int nrhs, double* __restrict__ stage,
+                             int stage_cap) {
+    const int p = bd.rank;
+    const int total = p * nrhs;                           // outputs, rhs-major
+    const int nit = bd.nitems;
+    const double* src = kp.partial + kp.citems[bd.item0].poff * nrhs;   // item c at src + c * total
+    double* dst = kp.T + bd.t_off * nrhs;
+    if (nit > stage_cap) {
+        for (int r = threadIdx.x; r < total; r += kThreads) {
+            CT s = CT(0);
+#pragma unroll 8
+            for (int c = 0; c < nit; ++c) s += CT(ld_coh(src + int64_t(c) * total + r));
+            st_coh(dst + r, double(s) * kp.tscale[bd.ts_off + r % p]);
+        }
+        return;
+    }
+    const int oc_max = stage_cap / nit;
+    for (int o0 = 0; o0 < total; o0 += oc_max) {
+        const int oc = (total - o0) < oc_max ? (total - o0) : oc_max;
+        for (int e = threadIdx.x; e < nit * oc; e += kThreads) {
+            const int c = e / oc, r = e - c * oc;
+            stage[e] = ld_coh(src + int64_t(c) * total + o0 + r);
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < oc; r += kThreads) {
+            CT s = CT(0);
+            for (int c = 0; c < nit; ++c) s += CT(stage[c * oc + r]);
+            st_coh(dst + o0 + r, double(s) * kp.tscale[bd.ts_off + (o0 + r) % p]);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename XT, typename AT, int RG>
+__device__ void run_contract(const KParams& kp, int item, const XT* __restrict__ X, int64_t ldx, int nrhs,
+                             unsigned char* smem, int* s_flag, int stage_cap) {
+    const CItem it = kp.citems[item];
+    const BlockDesc bd = kp.blocks[it.block];
+    run_contract_item<XT, AT, RG>(kp, it, bd, X, ldx, nrhs);
+    // publish: the partial's stores complete before the arrival is counted;
+    // the last arrival reduces the block and clears the counter for the next
+    // launch (nobody else touches it in this one)
     drain_and_sync();
     if (threadIdx.x == 0) *s_flag = (add_coh(arrivals(kp) + it.block, 1) == bd.nitems - 1);
     __syncthreads();
     if (*s_flag) {
+        double* stage = reinterpret_cast<double*>(smem);
         if (bd.fmt == F64)
-            finish_block<double>(kp, bd, nrhs);
+            finish_block<double>(kp, bd, nrhs, stage, stage_cap);
         else
-            finish_block<AT>(kp, bd, nrhs);
-        drain_and_sync();
-        if (threadIdx.x == 0) st_coh(ready(kp) + it.block, 1);
+            finish_block<AT>(kp, bd, nrhs, stage, stage_cap);
+        if (threadIdx.x == 0) st_coh(arrivals(kp) + it.block, 0);
     }
 }
 
 // ---------------------------------------------------------------------------
 // expansion tile: Y rows of one leaf = D_i x_i + sum_k U_b T_b
 // ---------------------------------------------------------------------------
+// chunk0: node-relative padded row where the tile's chunk of the U panel
+// starts; rin: the lane's first row within the tile; ld: tile rows.
 template <int F, typename CT, typename AT, int RG, int RPL>
-__device__ void expand_level(const KParams& kp, const BlockDesc& bd, int prow, bool act,
+__device__ void expand_level(const KParams& kp, const BlockDesc& bd, int chunk0, int rin, int ld, bool act,
                              const double* __restrict__ ts, AT acc[RPL][RG]) {
     constexpr int S = Codec<F>::kBytes;
+    constexpr int UN = sizeof(CT) == 8 ? kUnroll / 2 : kUnroll;   // columns in flight
     const int wave = threadIdx.x >> 6;
     const int p = bd.rank;
-    const uint8_t* Up = kp.fac + bd.u_off + int64_t(prow) * S;
-    const int64_t ld = bd.urows;
+    const uint8_t* Up = kp.fac + bd.u_off + (int64_t(chunk0) * p + rin) * S;
     CT lacc[RPL][RG];
 #pragma unroll
     for (int i = 0; i < RPL; ++i)
 #pragma unroll
         for (int rg = 0; rg < RG; ++rg) lacc[i][rg] = CT(0);
     int j = wave;
-    for (; j + 3 * kWaves < p; j += 4 * kWaves) {
-        CT u[4][RPL];
+    for (; j + (UN - 1) * kWaves < p; j += UN * kWaves) {
+        CT u[UN][RPL];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < UN; ++q) {
             if (act)
                 Codec<F>::template load<RPL, CT>(Up + int64_t(j + q * kWaves) * ld * S, u[q]);
             else
@@ -409,7 +423,7 @@ __device__ void expand_level(const KParams& kp, const BlockDesc& bd, int prow, b
                 for (int i = 0; i < RPL; ++i) u[q][i] = CT(0);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < UN; ++q)
 #pragma unroll
             for (int rg = 0; rg < RG; ++rg) {
                 const CT tv = CT(ts[rg * p + j + q * kWaves]);
@@ -439,8 +453,7 @@ __device__ void expand_level(const KParams& kp, const BlockDesc& bd, int prow, b
 
 template <typename XT, typename AT, int RG, int RPL>
 __device__ void run_expand(const KParams& kp, int tile, const XT* __restrict__ X, int64_t ldx,
-                           XT* __restrict__ Y, int64_t ldy, int nrhs, unsigned char* smem, int* s_off,
-                           int* s_err) {
+                           XT* __restrict__ Y, int64_t ldy, int nrhs, unsigned char* smem, int* s_off) {
     constexpr int TR = 64 * RPL;                    // rows per tile
     const ETile t = kp.etiles[tile];
     const LeafDesc L = kp.leaves[t.leaf];
@@ -452,17 +465,23 @@ __device__ void run_expand(const KParams& kp, int tile, const XT* __restrict__ X
     // LDS: x of the leaf [m][RG] | T of every level [sum p][RG] | wave sums [kWaves][TR]
     double* xs = reinterpret_cast<double*>(smem);
     double* ts = xs + int64_t(L.m) * RG;
+    // level offsets of T in LDS: thread k-1 reads level k's rank, thread 0 adds up
+    if (threadIdx.x < depth) {
+        const int k = threadIdx.x + 1;
+        s_off[k] = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))].rank * RG;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         int off = 0;
         for (int k = 1; k <= depth; ++k) {
+            const int r = s_off[k];
             s_off[k - 1] = off;
-            off += kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))].rank * RG;
+            off += r;
         }
         s_off[depth] = off;
     }
     __syncthreads();
     AT* red = reinterpret_cast<AT*>(ts + s_off[depth]);
-    bool waited_ok = true;
     for (int rb = 0; rb < nrhs; rb += RG) {
         for (int idx = threadIdx.x; idx < L.m * RG; idx += kThreads) {
             const int c = idx / RG, rg = idx % RG;
@@ -476,13 +495,14 @@ __device__ void run_expand(const KParams& kp, int tile, const XT* __restrict__ X
             for (int i = 0; i < RPL; ++i)
 #pragma unroll
                 for (int rg = 0; rg < RG; ++rg) dacc[i][rg] = 0.0;
-            const uint8_t* Dp = reinterpret_cast<const uint8_t*>(kp.leafd + L.d_off + row);
-            const int64_t ldb = int64_t(L.mp) * 8;
+            // the tile's chunk of D_i: column-major, ld = t.nr
+            const uint8_t* Dp = reinterpret_cast<const uint8_t*>(kp.leafd + L.d_off + int64_t(t.r0) * L.mp + RPL * lane);
+            const int64_t ldb = int64_t(t.nr) * 8;
             int c = wave;
-            for (; c + 3 * kWaves < L.m; c += 4 * kWaves) {
-                double d[4][RPL];
+            for (; c + (kLeafUnroll - 1) * kWaves < L.m; c += kLeafUnroll * kWaves) {
+                double d[kLeafUnroll][RPL];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < kLeafUnroll; ++q) {
                     if (act)
                         Codec<F64>::template load<RPL, double>(Dp + int64_t(c + q * kWaves) * ldb, d[q]);
                     else
@@ -490,7 +510,7 @@ __device__ void run_expand(const KParams& kp, int tile, const XT* __restrict__ X
                         for (int i = 0; i < RPL; ++i) d[q][i] = 0.0;
                 }
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < kLeafUnroll; ++q)
 #pragma unroll
                     for (int rg = 0; rg < RG; ++rg) {
                         const double xv = xs[(c + q * kWaves) * RG + rg];
@@ -517,42 +537,31 @@ __device__ void run_expand(const KParams& kp, int tile, const XT* __restrict__ X
 #pragma unroll
                 for (int rg = 0; rg < RG; ++rg) acc[i][rg] = AT(dacc[i][rg]);
         }
-        if (rb == 0) {
-            // T of every ancestor level: thread k-1 waits for level k's block
-            if (threadIdx.x < depth) {
-                const int k = threadIdx.x + 1;
-                const int b = (1 << k) - 2 + (t.leaf >> (depth - k));
-                if (kp.blocks[b].rank > 0 && !wait_ready(ready(kp) + b)) {
-                    atomicOr(kp.sync + 2, 1);
-                    *s_err = 1;
-                }
-            }
-            __syncthreads();
-            waited_ok = *s_err == 0;
-        }
-        for (int k = 1; k <= depth; ++k) {
-            const int b = (1 << k) - 2 + (t.leaf >> (depth - k));
-            const BlockDesc& bd = kp.blocks[b];
+        // T of every level for right-hand sides [rb, rb+RG): one pass of loads
+        for (int idx = threadIdx.x; idx < s_off[depth]; idx += kThreads) {
+            int k = 1;
+            while (k < depth && s_off[k] <= idx) ++k;
+            const BlockDesc& bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
             const int p = bd.rank;
-            for (int idx = threadIdx.x; idx < p * RG; idx += kThreads) {
-                const int rg = idx / p, j = idx % p;
-                ts[s_off[k - 1] + idx] = (rb + rg < nrhs) ? ld_coh(kp.T + bd.t_off * nrhs + int64_t(rb + rg) * p + j) : 0.0;
-            }
+            const int r = idx - s_off[k - 1];
+            const int rg = r / p, j = r - rg * p;
+            ts[idx] = (rb + rg < nrhs) ? kp.T[bd.t_off * nrhs + int64_t(rb + rg) * p + j] : 0.0;
         }
         __syncthreads();
         for (int k = 1; k <= depth; ++k) {
             const int b = (1 << k) - 2 + (t.leaf >> (depth - k));
             const BlockDesc bd = kp.blocks[b];
             if (bd.rank == 0) continue;
-            const int prow = L.prow0 - bd.urow0 + row;
+            const int c0 = L.prow0 - bd.urow0 + t.r0;
+            const int rin = RPL * lane;
             const double* tk = ts + s_off[k - 1];
             switch (bd.fmt) {
-                case F64: expand_level<F64, double, AT, RG, RPL>(kp, bd, prow, act, tk, acc); break;
-                case F32: expand_level<F32, AT, AT, RG, RPL>(kp, bd, prow, act, tk, acc); break;
-                case BF16: expand_level<BF16, AT, AT, RG, RPL>(kp, bd, prow, act, tk, acc); break;
-                case F16: expand_level<F16, AT, AT, RG, RPL>(kp, bd, prow, act, tk, acc); break;
-                case E4M3: expand_level<E4M3, AT, AT, RG, RPL>(kp, bd, prow, act, tk, acc); break;
-                default: expand_level<E5M2, AT, AT, RG, RPL>(kp, bd, prow, act, tk, acc); break;
+                case F64: expand_level<F64, double, AT, RG, RPL>(kp, bd, c0, rin, t.nr, act, tk, acc); break;
+                case F32: expand_level<F32, AT, AT, RG, RPL>(kp, bd, c0, rin, t.nr, act, tk, acc); break;
+                case BF16: expand_level<BF16, AT, AT, RG, RPL>(kp, bd, c0, rin, t.nr, act, tk, acc); break;
+                case F16: expand_level<F16, AT, AT, RG, RPL>(kp, bd, c0, rin, t.nr, act, tk, acc); break;
+                case E4M3: expand_level<E4M3, AT, AT, RG, RPL>(kp, bd, c0, rin, t.nr, act, tk, acc); break;
+                default: expand_level<E5M2, AT, AT, RG, RPL>(kp, bd, c0, rin, t.nr, act, tk, acc); break;
             }
         }
         // sum the waves' partial rows; write Y once
@@ -567,7 +576,7 @@ __device__ void run_expand(const KParams& kp, int tile, const XT* __restrict__ X
                 for (int w = 1; w < kWaves; ++w) s += red[w * TR + r];
                 const int lr = t.r0 + r;
                 if (r < t.nr && lr < L.m && rb + rg < nrhs)
-                    Y[L.row0 + lr + ldy * (rb + rg)] = waited_ok ? XT(s) : XT(__builtin_nan(""));
+                    Y[L.row0 + lr + ldy * (rb + rg)] = XT(s);
             }
             __syncthreads();
         }
@@ -575,40 +584,24 @@ __device__ void run_expand(const KParams& kp, int tile, const XT* __restrict__ X
 }
 
 // ---------------------------------------------------------------------------
-// the fused launch
+// the two launches
 // ---------------------------------------------------------------------------
+template <typename XT, typename AT, int RG>
+__global__ __launch_bounds__(kThreads, HODLR_CONTRACT_MINW) void k_contract(KParams kp, const XT* __restrict__ Xc, int64_t ldc,
+                                                       int nrhs, int stage_cap) {
+    extern __shared__ double smem_d[];
+    __shared__ int s_flag;
+    run_contract<XT, AT, RG>(kp, blockIdx.x, Xc, ldc, nrhs, reinterpret_cast<unsigned char*>(smem_d), &s_flag,
+                             stage_cap);
+}
+
 template <typename XT, typename AT, int RG, int RPL>
-__global__ __launch_bounds__(kThreads, 4) void k_matvec(KParams kp, const XT* __restrict__ Xc, int64_t ldc,
-                                                     const XT* __restrict__ X, int64_t ldx,
+__global__ __launch_bounds__(kThreads, HODLR_EXPAND_MINW) void k_expand(KParams kp, const XT* __restrict__ X, int64_t ldx,
                                                      XT* __restrict__ Y, int64_t ldy, int nrhs) {
     extern __shared__ double smem_d[];
-    unsigned char* smem = reinterpret_cast<unsigned char*>(smem_d);
-    __shared__ int s_ticket, s_flag, s_err;
     __shared__ int s_off[kMaxDepth + 1];
-    if (threadIdx.x == 0) {
-        s_ticket = add_coh(kp.sync, 1);
-        s_err = 0;
-    }
-    __syncthreads();
-    const int ticket = s_ticket;
-    if (ticket < kp.ncitems) {
-        run_contract<XT, AT, RG>(kp, ticket, Xc, ldc, nrhs, smem, &s_flag);
-    } else if (ticket < kp.ncitems + kp.netiles) {
-        run_expand<XT, AT, RG, RPL>(kp, ticket - kp.ncitems, X, ldx, Y, ldy, nrhs, smem, s_off, &s_err);
-    } else if (threadIdx.x == 0) {
-        atomicOr(kp.sync + 2, 2);   // counters were not clear: flag it, touch nothing
-    }
-    // the last workgroup to finish clears the counters for the next launch
-    __syncthreads();
-    if (threadIdx.x == 0) s_flag = (add_coh(kp.sync + 1, 1) == kp.ncitems + kp.netiles - 1);
-    __syncthreads();
-    if (s_flag) {
-        for (int i = threadIdx.x; i < 2 * kp.nblocks; i += kThreads) st_coh(kp.sync + kSyncHead + i, 0);
-        if (threadIdx.x == 0) {
-            st_coh(kp.sync, 0);
-            st_coh(kp.sync + 1, 0);
-        }
-    }
+    run_expand<XT, AT, RG, RPL>(kp, blockIdx.x, X, ldx, Y, ldy, nrhs, reinterpret_cast<unsigned char*>(smem_d),
+                                s_off);
 }
 
 // ---------------------------------------------------------------------------
@@ -642,11 +635,16 @@ struct Timer {            // optional event pair around each phase
 
 constexpr int kRPL = kTileRows / 64;       // rows per lane in expansion tiles
 
-size_t lds_need(const KParams& kp, int rg, size_t acc_bytes) {
-    const size_t cj = kContractCols / rg > 1 ? kContractCols / rg : 2;    // an upper bound
-    const size_t c = kWaves * cj * rg * 8;
-    const size_t e = (size_t(kp.max_leaf) + size_t(kp.max_rank_path)) * rg * 8 + kWaves * kTileRows * acc_bytes;
-    return c > e ? c : e;
+constexpr int kStageMax = 4096;   // doubles of LDS for staging a block's partials
+
+int stage_cap(const KParams& kp, int rg) {
+    const int64_t need = int64_t(kp.max_items_rank) * rg;
+    return int(need < kStageMax ? (need > 0 ? need : 1) : kStageMax);
+}
+
+// expansion tile LDS: x of the leaf | T of its levels (doubles) | wave sums
+size_t lds_expand(const KParams& kp, int rg, size_t acc_bytes) {
+    return (size_t(kp.max_leaf) + size_t(kp.max_rank_path)) * rg * 8 + size_t(kWaves) * kTileRows * acc_bytes;
 }
 
 template <typename XT, typename AT, int RG, int RPL>
@@ -664,13 +662,17 @@ hipError_t launch_typed(const KParams& kp, const void* Xv, int64_t ldx, void* Yv
         Xc = static_cast<const XT*>(kp.xpad);
         ldc = kp.npad;
     }
-    // dynamic LDS: the larger of the contraction's wave sums and the tile's
-    // x | T | wave-sum regions
-    const size_t lds = lds_need(kp, RG, sizeof(AT));
-    tm.begin(1);
-    hipLaunchKernelGGL((k_matvec<XT, AT, RG, RPL>), dim3(kp.ncitems + kp.netiles), dim3(kThreads), lds, s, kp,
-                       Xc, ldc, X, ldx, Y, ldy, nrhs);
-    tm.end(1);
+    if (kp.ncitems > 0) {
+        const int sc = stage_cap(kp, RG);
+        tm.begin(1);
+        hipLaunchKernelGGL((k_contract<XT, AT, RG>), dim3(kp.ncitems), dim3(kThreads), size_t(sc) * 8, s, kp, Xc,
+                           ldc, nrhs, sc);
+        tm.end(1);
+    }
+    tm.begin(2);
+    hipLaunchKernelGGL((k_expand<XT, AT, RG, RPL>), dim3(kp.netiles), dim3(kThreads), lds_expand(kp, RG, sizeof(AT)),
+                       s, kp, X, ldx, Y, ldy, nrhs);
+    tm.end(2);
     return hipGetLastError();
 }
 
@@ -679,8 +681,8 @@ hipError_t launch_rg(const KParams& kp, const void* X, int64_t ldx, void* Y, int
                      const Timer& tm) {
     // the widest right-hand-side group whose LDS fits in 64 KB
     int rg = nrhs == 1 ? 1 : nrhs == 2 ? 2 : nrhs <= 4 ? 4 : 8;
-    while (rg > 1 && lds_need(kp, rg, sizeof(AT)) > kMaxLds) rg /= 2;
-    if (lds_need(kp, rg, sizeof(AT)) > kMaxLds) return hipErrorInvalidConfiguration;
+    while (rg > 1 && lds_expand(kp, rg, sizeof(AT)) > kMaxLds) rg /= 2;
+    if (lds_expand(kp, rg, sizeof(AT)) > kMaxLds) return hipErrorInvalidConfiguration;
     if (rg == 1) return launch_typed<XT, AT, 1, kRPL>(kp, X, ldx, Y, ldy, nrhs, tm);
     if (rg == 2) return launch_typed<XT, AT, 2, kRPL>(kp, X, ldx, Y, ldy, nrhs, tm);
     if (rg == 4) return launch_typed<XT, AT, 4, kRPL>(kp, X, ldx, Y, ldy, nrhs, tm);
