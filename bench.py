@@ -14,9 +14,14 @@ as one JSON line:
           + n nrhs (s_X + s_Y)
   (leaves, factor codes, scales, X read once, Y written once);
 * gflops: F_alg / time, F_alg = 2 nrhs (sum m_i^2 + sum_b (r_b + c_b) p_b);
-* roofline: the product is one fused kernel; its algorithmic bytes per
-  launch (B_alg) over its mean duration from HIP events recorded around it
-  on its stream during the timed steps;
+* roofline: the dominant kernel, k_expand (fp64 leaves, U codes, X and Y:
+  8 sum m_i^2 + sum_b r_b p_b s(f_b) + n nrhs (s_X + s_Y) bytes per
+  launch), over its mean duration from HIP events the library records
+  around it on its launch stream (an eager loop of the same products);
+  k_contract (sum_b c_b p_b s(f_b) + n nrhs s_X bytes) is reported beside it;
+* timing: the K timed products are captured once into a HIP graph and
+  replayed between two events, so the timed region holds exactly K
+  products and no Python launch latency;
 * speedup_vs_fp64: same operator with every level stored in fp64 and fp64
   accumulation (the uniform-precision product on the same GPU);
 * cpu_baseline: the CPU oracle's fp64 product of the same stored operator
@@ -39,7 +44,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matvec_c2.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_expand_c2_nrhs1.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2407_21637_amd", "csrc", "kernels.hip")
 
 
@@ -49,6 +54,17 @@ def log(*a):
 
 def kernel_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """key: value lines of the counter summary (HBM bytes per launch)."""
+    out = {}
+    if os.path.exists(TRAFFIC_FILE):
+        for line in open(TRAFFIC_FILE):
+            k, sep, v = line.partition(":")
+            if sep and k.strip() and " " not in k.strip():
+                out[k.strip()] = v.strip()
+    return out
 
 
 def build_operator(cfg, H):
@@ -65,35 +81,65 @@ def build_operator(cfg, H):
     return P, blocks, leaves, op
 
 
+SBYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2, "e4m3": 1, "e5m2": 1}
+
+
 def work(h, n, nrhs, xy_bytes):
+    """Algorithmic bytes and flops of one product, and per kernel."""
     inf = h.info()
     B = inf["leaf_bytes"] + inf["factor_bytes"] + inf["scale_bytes"] + n * nrhs * 2 * xy_bytes
-    lr = 0
+    lr = ub = vb = 0
     for b in range(h.nblocks):
         bi = h.block(b)
+        s = SBYTES[bi["dtype"]]
         lr += (bi["nrows"] + bi["ncols"]) * bi["rank"]
+        ub += bi["nrows"] * bi["rank"] * s
+        vb += bi["ncols"] * bi["rank"] * s
     F = 2 * nrhs * (inf["leaf_bytes"] // 8 + lr)
-    return B, F, B
+    expand = inf["leaf_bytes"] + ub + n * nrhs * 2 * xy_bytes
+    contract = vb + n * nrhs * xy_bytes
+    return B, F, expand, contract
 
 
-def time_steps(h, X, Y, steps, warmup, torch, profile=True):
-    for _ in range(warmup):
-        h.matvec(X, Y)
+def time_steps(h, X, Y, steps, warmup, torch):
+    """ms per product: K products captured in one HIP graph, replayed."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(max(warmup, 1)):     # also sizes this stream's workspace
+            h.matvec(X, Y)
     torch.cuda.synchronize()
-    if profile:
-        h.profile(steps)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for _ in range(steps):
+            h.matvec(X, Y)
+    torch.cuda.synchronize()
+    g.replay()                              # untimed: first replay of the graph
+    torch.cuda.synchronize()
+    cs = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    e0.record()
-    for _ in range(steps):
-        h.matvec(X, Y)
-    e1.record()
+    e0.record(cs)
+    g.replay()                              # exactly `steps` products
+    e1.record(cs)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    phases = h.profile_read() if profile else None
-    if profile:
-        h.profile(0)
-    return ms, phases
+    del g
+    return ms
+
+
+def time_phases(h, X, Y, reps, torch):
+    """Mean per-kernel durations (us) from the library's event hook, eager."""
+    for _ in range(3):
+        h.matvec(X, Y)
+    torch.cuda.synchronize()
+    h.profile(reps)
+    for _ in range(reps):
+        h.matvec(X, Y)
+    torch.cuda.synchronize()
+    ph = h.profile_read()
+    h.profile(0)
+    return {k: v[0] / v[1] * 1e3 for k, v in ph.items() if v[1]}
 
 
 def time_cold(h, X, Y, reps, torch):
@@ -147,6 +193,10 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the timed products (for running under rocprofv3)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 256 MiB device-to-device copy 5 times (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: the product shards by subtree with a "
@@ -160,6 +210,14 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.copy_calibration:
+        a = torch.ones(1 << 26, dtype=torch.float32, device="cuda:0")
+        c = torch.empty_like(a)
+        for _ in range(5):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "copies": 5}), flush=True)
+        return
     H.lib()   # fail loudly if the HIP library is not built
     dev = torch.device("cuda:0")
     cfg = CF.get(args.workload)
@@ -175,35 +233,40 @@ def main():
     xb = 4 if cfg.x_dtype == "fp32" else 8
     Xh = cfg.X(max(args.nrhs, 32))
     results = {}
-    for nrhs in sorted({args.nrhs, 32}):
+    nrhs_list = [args.nrhs] if args.profile_run else sorted({args.nrhs, 32})
+    for nrhs in nrhs_list:
         X = H.colmajor_empty(cfg.n, nrhs, xdt, dev)
         X.copy_(torch.from_numpy(np.asfortranarray(Xh[:, :nrhs])).to(xdt))
         Y = H.colmajor_empty(cfg.n, nrhs, xdt, dev)
-        B, Fl, EB = work(h, cfg.n, nrhs, xb)
-        ms, ph = time_steps(h, X, Y, args.steps, args.warmup, torch)
+        B, Fl, EB, CB = work(h, cfg.n, nrhs, xb)
+        ms = time_steps(h, X, Y, args.steps, args.warmup, torch)
+        ph = time_phases(h, X, Y, 50, torch)
         cold = time_cold(h, X, Y, 10, torch)
-        results[nrhs] = dict(ms=ms, phases=ph, B=B, F=Fl, EB=EB, cold_ms=cold, X=X, Y=Y)
+        results[nrhs] = dict(ms=ms, phases=ph, B=B, F=Fl, EB=EB, CB=CB, cold_ms=cold, X=X, Y=Y)
         log(f"[bench] nrhs={nrhs}: {ms * 1e3:.1f} us/step, {B / ms / 1e6:.1f} GB/s, cold {cold * 1e3:.1f} us, "
-            f"phases {ph}")
+            f"kernels (us) {ph}")
+    if args.profile_run:
+        print(json.dumps({"profile_run": True, "us_per_step": results[args.nrhs]["ms"] * 1e3}), flush=True)
+        return
 
     # uniform-fp64 product on the same GPU, same ranks
     h.set_level_precisions(["fp64"] * cfg.depth, H.ACC_FP64)
     r0 = results[args.nrhs]
-    ms64, _ = time_steps(h, r0["X"], r0["Y"], args.steps, args.warmup, torch, profile=False)
-    B64, _, _ = work(h, cfg.n, args.nrhs, xb)
+    ms64 = time_steps(h, r0["X"], r0["Y"], args.steps, args.warmup, torch)
+    B64 = work(h, cfg.n, args.nrhs, xb)[0]
     h.assign_precision(cfg.eps, cfg.allowed, norms2)
     log(f"[bench] uniform fp64: {ms64 * 1e3:.1f} us/step")
 
     r = results[args.nrhs]
-    ph = r["phases"]["matvec"]
-    exp_ms = ph[0] / max(ph[1], 1)
-    achieved = r["EB"] / (exp_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel_sha") == kernel_hash() and tr.get("workload") == cfg.name and \
-                tr.get("nrhs") == args.nrhs:
-            traffic = tr.get("bytes_per_launch")
+    exp_us = r["phases"]["expand"]
+    con_us = r["phases"].get("contract", 0.0)
+    achieved = r["EB"] / (exp_us * 1e-6) / 1e9
+    traffic = traffic_c = None
+    tr = read_traffic()
+    if tr.get("kernel_sha") == kernel_hash() and tr.get("workload") == cfg.name and \
+            tr.get("nrhs") == str(args.nrhs) and "k_expand_bytes_per_launch" in tr:
+        traffic = int(tr["k_expand_bytes_per_launch"])
+        traffic_c = int(tr.get("k_contract_bytes_per_launch", 0)) or None
     value = r["B"] / (r["ms"] * 1e-3) / 1e9
     out = {
         "metric": "HODLR matvec GB/s & Gflop/s (% roofline); speedup mixed vs FP64 at fixed eps",
@@ -229,17 +292,21 @@ def main():
         "cold_cache_gbs": round(r["B"] / (r["cold_ms"] * 1e-3) / 1e9, 2),
         "speedup_vs_fp64": round(ms64 / r["ms"], 3),
         "fp64_gbs": round(B64 / (ms64 * 1e-3) / 1e9, 2),
-        "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in r["phases"].items() if v[1]},
-        "roofline": {"bound": "hbm", "kernel": "k_matvec (fused product)",
+        "kernels_us": {k: round(v, 2) for k, v in r["phases"].items()},
+        "roofline": {"bound": "hbm", "kernel": "k_expand (fp64 leaf GEMV + expansion, writes Y)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "alg_bytes_per_launch": int(r["EB"]), "mean_launch_us": round(exp_ms * 1e3, 2)},
+                     "alg_bytes_per_launch": int(r["EB"]), "mean_launch_us": round(exp_us, 2)},
+        "contract_kernel": {"alg_bytes_per_launch": int(r["CB"]), "mean_launch_us": round(con_us, 2),
+                            "achieved_gbs": round(r["CB"] / (con_us * 1e-6) / 1e9, 2) if con_us else None,
+                            "traffic": traffic_c},
     }
     if 32 in results and args.nrhs != 32:
         r32 = results[32]
         out["nrhs32"] = {"gbs": round(r32["B"] / (r32["ms"] * 1e-3) / 1e9, 2),
                          "gflops": round(r32["F"] / (r32["ms"] * 1e-3) / 1e9, 2),
-                         "ms_per_step": round(r32["ms"], 5)}
+                         "ms_per_step": round(r32["ms"], 5),
+                         "kernels_us": {k: round(v, 2) for k, v in r32["phases"].items()}}
     if not args.no_cpu:
         Xc = Xh[:, :args.nrhs]
         cb, y_ora, U, V, oblocks, lb = cpu_baseline(cfg, blocks, leaves, op, fmts, r["B"], Xc)
