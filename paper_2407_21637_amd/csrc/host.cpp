@@ -985,7 +985,9 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
     Workspace& w = op->ws[stream];
     const int64_t need_p = std::max<int64_t>(1, op->total_item_rank * nrhs);
     const int64_t need_t = std::max<int64_t>(1, op->total_rank * nrhs);
-    const int64_t need_x = op->padded ? op->npad * nrhs * (xy_double ? 8 : 4) : 0;
+    // padded X: when some leaf is padded, and for the matrix-core path (nrhs >= 16),
+    // which reads X with 16-byte vector loads and copies it when it is not aligned
+    const int64_t need_x = (op->padded || nrhs >= 16) ? op->npad * nrhs * (xy_double ? 8 : 4) : 0;
     auto grow = [&](void** ptr, int64_t* cap, int64_t bytes, const char* what) -> hodlr_status {
         if (bytes <= *cap) return HODLR_OK;
         if (*ptr) {

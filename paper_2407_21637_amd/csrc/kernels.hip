@@ -689,18 +689,415 @@ hipError_t launch_rg(const KParams& kp, const void* X, int64_t ldx, void* Y, int
     return launch_typed<XT, AT, 8, kRPL>(kp, X, ldx, Y, ldy, nrhs, tm);
 }
 
+// ---------------------------------------------------------------------------
+// many right-hand sides: MFMA tiles
+// ---------------------------------------------------------------------------
+// With nrhs >= kWideMin the leaf products are dense fp64 GEMMs and the
+// low-rank products skinny GEMMs, so both phases run on the matrix cores:
+// v_mfma_f64_16x16x4f64 for the leaves and fp64 levels, v_mfma_f32_16x16x4f32
+// for levels decoded to fp32.  In both, A is 16x4 with A[l%16][l/16] in lane
+// l and B is 4x16 with B[l/16][l%16] in lane l.  Element e of lane l of the
+// 16x16 result is C[4*(l/16)+e][l%16] for fp32 but C[l/16+4e][l%16] for fp64
+// (measured on gfx950; see acc_row).  The reduction index only has
+// to agree between A and B, so lane l feeds its own kKL consecutive rows
+// (one vector load) to kKL successive MFMAs: lane group g = l/16 of a 32-row
+// step takes rows 8g..8g+7.
+constexpr int kWideMin = 16;
+constexpr int kKL = 8;                      // consecutive rows per lane per step
+constexpr int kStep = 4 * kKL;              // rows per MFMA step (4 lane groups)
+constexpr int kJC = 32;                     // T rows staged in LDS at a time
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+    using acc_t = f32x4;
+    __device__ static acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma<double> {
+    using acc_t = f64x4;
+    __device__ static acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+// row of the 16x16 result held in element e by lane group g = l/16
+template <typename CT>
+__device__ __forceinline__ int acc_row(int g, int e) {
+    return sizeof(CT) == 8 ? g + 4 * e : 4 * g + e;
+}
+
+// A-operand row that lane l%16 feeds so that an fp32 result lands in the
+// fp64 layout: output row 4g+e of the MFMA then holds tile row g+4e.
+__device__ __forceinline__ int f64_layout_row(int li) { return (li >> 2) + 4 * (li & 3); }
+
+template <typename A>
+__device__ __forceinline__ void zero_acc(A& a) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] = 0;
+}
+
+// kKL consecutive codes of one column (8-element aligned)
+template <int F, typename CT>
+__device__ __forceinline__ void load_codes8(const uint8_t* p, CT v[kKL]) {
+    constexpr int S = Codec<F>::kBytes;
+    Codec<F>::template load<4, CT>(p, v);
+    Codec<F>::template load<4, CT>(p + 4 * S, v + 4);
+}
+
+// kKL consecutive right-hand-side values (16-byte aligned)
+template <typename XT, typename CT>
+__device__ __forceinline__ void load_x8(const XT* p, CT v[kKL]) {
+    if constexpr (sizeof(XT) == 4) {
+        const float4 a = reinterpret_cast<const float4*>(p)[0];
+        const float4 b = reinterpret_cast<const float4*>(p)[1];
+        v[0] = CT(a.x); v[1] = CT(a.y); v[2] = CT(a.z); v[3] = CT(a.w);
+        v[4] = CT(b.x); v[5] = CT(b.y); v[6] = CT(b.z); v[7] = CT(b.w);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double2 a = reinterpret_cast<const double2*>(p)[i];
+            v[2 * i] = CT(a.x);
+            v[2 * i + 1] = CT(a.y);
+        }
+    }
+}
+
+// Contraction item on the matrix cores: partial T_b over rows [r0, r0+nr)
+// of the V panel for right-hand sides [c0, c0 + 16 NT).  The waves split
+// the rows in 32-row steps; each keeps a (16 PG) x (16 NT) block of partial
+// sums per pass over the rank and the four are added in LDS (`red`).
+template <int F, typename CT, typename XT, int NT>
+__device__ void contract_item_w(const KParams& kp, const CItem& it, const BlockDesc& bd,
+                                const XT* __restrict__ X, int64_t ldx, int nrhs, int c0, CT* red) {
+    using M = Mfma<CT>;
+    constexpr int S = Codec<F>::kBytes;
+    constexpr int PG = sizeof(CT) == 8 ? 2 : 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    const int p = bd.rank;
+    const uint8_t* Vp = kp.fac + bd.v_off + int64_t(it.r0) * p * S;
+    const int64_t ld = it.nr;
+    double* part = kp.partial + it.poff * nrhs;
+    const XT* Xr = X + int64_t(bd.vrow0) + it.r0;
+    const int nstep = (it.nr + kStep - 1) / kStep;
+    for (int j0 = 0; j0 < p; j0 += 16 * PG) {
+        typename M::acc_t acc[PG][NT];
+#pragma unroll
+        for (int a = 0; a < PG; ++a)
+#pragma unroll
+            for (int b = 0; b < NT; ++b) zero_acc(acc[a][b]);
+        for (int st = wave; st < nstep; st += kWaves) {
+            const int row = st * kStep + g * kKL;       // nr and row are multiples of 8
+            const bool ok = row < it.nr;
+            CT a[PG][kKL], b[NT][kKL];
+#pragma unroll
+            for (int pg = 0; pg < PG; ++pg) {
+                const int j = j0 + 16 * pg + li;
+                if (ok && j < p)
+                    load_codes8<F, CT>(Vp + (int64_t(j) * ld + row) * S, a[pg]);
+                else
+#pragma unroll
+                    for (int q = 0; q < kKL; ++q) a[pg][q] = CT(0);
+            }
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+                const int c = c0 + 16 * ct + li;
+                if (ok && c < nrhs)
+                    load_x8<XT, CT>(Xr + row + ldx * c, b[ct]);
+                else
+#pragma unroll
+                    for (int q = 0; q < kKL; ++q) b[ct][q] = CT(0);
+            }
+#pragma unroll
+            for (int q = 0; q < kKL; ++q)
+#pragma unroll
+                for (int pg = 0; pg < PG; ++pg)
+                    if (j0 + 16 * pg < p)
+#pragma unroll
+                        for (int ct = 0; ct < NT; ++ct) acc[pg][ct] = M::mma(a[pg][q], b[ct][q], acc[pg][ct]);
+        }
+        // add the four waves' blocks, one rank tile at a time
+#pragma unroll
+        for (int pg = 0; pg < PG; ++pg) {
+            if (j0 + 16 * pg >= p) break;
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    red[(wave * NT + ct) * 256 + acc_row<CT>(g, e) * 16 + li] = acc[pg][ct][e];
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < NT * 256; idx += kThreads) {
+                const int ct = idx >> 8, jr = (idx >> 4) & 15, cl = idx & 15;
+                const int j = j0 + 16 * pg + jr, c = c0 + 16 * ct + cl;
+                CT s = CT(0);
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) s += red[(w * NT) * 256 + idx];
+                if (j < p && c < nrhs) st_coh(part + int64_t(c) * p + j, double(s));
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <typename XT, typename AT, int NT>
+__global__ __launch_bounds__(kThreads) void k_contract_w(KParams kp, const XT* __restrict__ Xc, int64_t ldc,
+                                                         int nrhs, int stage_cap) {
+    extern __shared__ double smem_d[];
+    __shared__ int s_flag;
+    const CItem it = kp.citems[blockIdx.x];
+    const BlockDesc bd = kp.blocks[it.block];
+    const int c0 = blockIdx.y * 16 * NT;
+    switch (bd.fmt) {
+        case F64: contract_item_w<F64, double, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<double*>(smem_d)); break;
+        case F32: contract_item_w<F32, AT, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<AT*>(smem_d)); break;
+        case BF16: contract_item_w<BF16, AT, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<AT*>(smem_d)); break;
+        case F16: contract_item_w<F16, AT, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<AT*>(smem_d)); break;
+        case E4M3: contract_item_w<E4M3, AT, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<AT*>(smem_d)); break;
+        default: contract_item_w<E5M2, AT, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<AT*>(smem_d)); break;
+    }
+    // every (item, right-hand-side group) workgroup of the block counts once
+    drain_and_sync();
+    if (threadIdx.x == 0)
+        s_flag = (add_coh(arrivals(kp) + it.block, 1) == bd.nitems * int(gridDim.y) - 1);
+    __syncthreads();
+    if (s_flag) {
+        double* stage = smem_d;
+        if (bd.fmt == F64)
+            finish_block<double>(kp, bd, nrhs, stage, stage_cap);
+        else
+            finish_block<AT>(kp, bd, nrhs, stage, stage_cap);
+        if (threadIdx.x == 0) st_coh(arrivals(kp) + it.block, 0);
+    }
+}
+
+// One level's U_b T_b added to a wave's two 16-row tiles (accumulators in
+// the fp64 row layout).  T_b is staged in LDS kJC rows at a time as
+// ts[j][c]; rows j >= p are zero.
+template <int F, typename CT, int NT>
+__device__ void expand_level_w(const KParams& kp, const BlockDesc& bd, int chunk0, int ld, int c0, int nrhs,
+                               bool act0, bool act1, CT* ts, typename Mfma<CT>::acc_t acc[2][NT]) {
+    using M = Mfma<CT>;
+    constexpr int S = Codec<F>::kBytes;
+    constexpr int CW = 16 * NT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    const int p = bd.rank;
+    const uint8_t* Up = kp.fac + bd.u_off + int64_t(chunk0) * p * S;
+    const double* Tb = kp.T + bd.t_off * nrhs;
+    // fp32 results are steered into the fp64 row layout of the accumulators
+    const int r0 = 32 * wave + (sizeof(CT) == 8 ? li : f64_layout_row(li)), r1 = r0 + 16;
+    for (int j0 = 0; j0 < p; j0 += kJC) {
+        __syncthreads();                                // previous users of ts are done
+        for (int idx = threadIdx.x; idx < kJC * CW; idx += kThreads) {
+            const int jr = idx / CW, cl = idx - jr * CW;
+            const int j = j0 + jr, c = c0 + cl;
+            ts[idx] = (j < p && c < nrhs) ? CT(Tb[int64_t(c) * p + j]) : CT(0);
+        }
+        __syncthreads();
+        CT a0[kKL], a1[kKL];
+#pragma unroll
+        for (int q = 0; q < kKL; ++q) {
+            const int j = j0 + g * kKL + q;
+            a0[q] = CT(0);
+            a1[q] = CT(0);
+            if (j < p) {
+                const uint8_t* col = Up + int64_t(j) * ld * S;
+                if (act0) Codec<F>::template load<1, CT>(col + int64_t(r0) * S, &a0[q]);
+                if (act1) Codec<F>::template load<1, CT>(col + int64_t(r1) * S, &a1[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kKL; ++q)
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+                const CT bv = ts[(g * kKL + q) * CW + 16 * ct + li];
+                acc[0][ct] = M::mma(a0[q], bv, acc[0][ct]);
+                acc[1][ct] = M::mma(a1[q], bv, acc[1][ct]);
+            }
+    }
+}
+
+template <typename CT, int NT>
+__device__ void expand_level_dispatch(const KParams& kp, const BlockDesc& bd, int chunk0, int ld, int c0, int nrhs,
+                                      bool act0, bool act1, CT* ts, typename Mfma<CT>::acc_t acc[2][NT]) {
+    switch (bd.fmt) {
+        case F64: expand_level_w<F64, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, acc); break;
+        case F32: expand_level_w<F32, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, acc); break;
+        case BF16: expand_level_w<BF16, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, acc); break;
+        case F16: expand_level_w<F16, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, acc); break;
+        case E4M3: expand_level_w<E4M3, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, acc); break;
+        default: expand_level_w<E5M2, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, acc); break;
+    }
+}
+
+// Expansion tile on the matrix cores: rows [r0, r0+nr) of leaf i (at most
+// 128, a multiple of 16) for right-hand sides [c0, c0 + 16 NT).  Wave w
+// owns tile rows 32w..32w+31 as two 16-row MFMA tiles.  The fp64 leaf GEMM
+// and every fp64 level accumulate in fp64; levels decoded to fp32 (when AT
+// is float) accumulate in fp32; the sum is rounded once into Y.
+template <typename XT, typename AT, int NT>
+__global__ __launch_bounds__(kThreads) void k_expand_w(KParams kp, const XT* __restrict__ Xw, int64_t ldw,
+                                                       XT* __restrict__ Y, int64_t ldy, int nrhs) {
+    extern __shared__ double smem_d[];
+    using MD = Mfma<double>;
+    const ETile t = kp.etiles[blockIdx.x];
+    const LeafDesc L = kp.leaves[t.leaf];
+    const int c0 = blockIdx.y * 16 * NT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    const int r0 = 32 * wave + li, r1 = r0 + 16;        // tile rows of the lane's A operands
+    const bool act0 = 32 * wave < t.nr, act1 = 32 * wave + 16 < t.nr;   // nr is a multiple of 16
+    MD::acc_t accd[2][NT];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) zero_acc(accd[a][b]);
+    // leaf: D_i (tile rows, all mp columns; column-major, ld = nr) times X_i
+    {
+        const double* Dp = kp.leafd + L.d_off + int64_t(t.r0) * L.mp;
+        const XT* Xl = Xw + L.prow0;
+        for (int k0 = 0; k0 < L.mp; k0 += kStep) {
+            const int k = k0 + g * kKL;                 // mp and k are multiples of 8
+            const bool ok = k < L.mp;
+            double a0[kKL], a1[kKL];
+            XT b[NT][kKL];
+#pragma unroll
+            for (int q = 0; q < kKL; ++q) {
+                a0[q] = (ok && act0) ? Dp[int64_t(k + q) * t.nr + r0] : 0.0;
+                a1[q] = (ok && act1) ? Dp[int64_t(k + q) * t.nr + r1] : 0.0;
+            }
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+                const int c = c0 + 16 * ct + li;
+                if (ok && c < nrhs)
+                    load_x8<XT, XT>(Xl + k + ldw * c, b[ct]);
+                else
+#pragma unroll
+                    for (int q = 0; q < kKL; ++q) b[ct][q] = XT(0);
+            }
+#pragma unroll
+            for (int q = 0; q < kKL; ++q)
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct) {
+                    accd[0][ct] = MD::mma(a0[q], double(b[ct][q]), accd[0][ct]);
+                    accd[1][ct] = MD::mma(a1[q], double(b[ct][q]), accd[1][ct]);
+                }
+        }
+    }
+    // the depth ancestors' blocks whose rows contain this leaf
+    typename Mfma<AT>::acc_t accl[2][NT];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) zero_acc(accl[a][b]);
+    const int depth = kp.depth;
+    for (int k = 1; k <= depth; ++k) {
+        const BlockDesc bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
+        if (bd.rank == 0) continue;
+        const int chunk0 = L.prow0 - bd.urow0 + t.r0;   // the tile's chunk of the U panel
+        if constexpr (sizeof(AT) == 8) {
+            expand_level_dispatch<double, NT>(kp, bd, chunk0, t.nr, c0, nrhs, act0, act1, smem_d, accd);
+        } else {
+            if (bd.fmt == F64)
+                expand_level_dispatch<double, NT>(kp, bd, chunk0, t.nr, c0, nrhs, act0, act1, smem_d, accd);
+            else
+                expand_level_dispatch<float, NT>(kp, bd, chunk0, t.nr, c0, nrhs, act0, act1,
+                                                 reinterpret_cast<float*>(smem_d), accl);
+        }
+    }
+    // Y rows g+4e of each 16-row tile (fp64 layout), column li of each column tile
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+            const int c = c0 + 16 * ct + li;
+            if (c >= nrhs) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int rr = 32 * wave + 16 * h + acc_row<double>(g, e);   // row within the tile
+                const int pr = t.r0 + rr;                                     // padded row within the leaf
+                if (rr < t.nr && pr < L.m)
+                    Y[L.row0 + pr + ldy * c] = XT(accd[h][ct][e] + double(accl[h][ct][e]));
+            }
+        }
+    }
+}
+
+size_t lds_contract_w(const KParams& kp, int nt, size_t acc_bytes, int sc) {
+    const size_t red = size_t(kWaves) * nt * 256 * acc_bytes;
+    const size_t stage = size_t(sc) * 8;
+    return red > stage ? red : stage;
+}
+
+template <typename XT, typename AT, int NT>
+hipError_t launch_wide_nt(const KParams& kp, const XT* Xw, int64_t ldw, XT* Y, int64_t ldy, int nrhs,
+                          const Timer& tm) {
+    hipStream_t s = tm.s;
+    constexpr int NTC = NT > 4 ? 4 : NT;                // contraction: at most 64 columns per workgroup
+    if (kp.ncitems > 0) {
+        const int sc = stage_cap(kp, 8);
+        const size_t acc_bytes = sizeof(double);        // fp64 levels use the same buffer
+        tm.begin(1);
+        hipLaunchKernelGGL((k_contract_w<XT, AT, NTC>), dim3(kp.ncitems, (nrhs + 16 * NTC - 1) / (16 * NTC)),
+                           dim3(kThreads), lds_contract_w(kp, NTC, acc_bytes, sc), s, kp, Xw, ldw, nrhs, sc);
+        tm.end(1);
+    }
+    tm.begin(2);
+    hipLaunchKernelGGL((k_expand_w<XT, AT, NT>), dim3(kp.netiles, (nrhs + 16 * NT - 1) / (16 * NT)), dim3(kThreads),
+                       size_t(kJC) * 16 * NT * sizeof(double), s, kp, Xw, ldw, Y, ldy, nrhs);
+    tm.end(2);
+    return hipGetLastError();
+}
+
+template <typename XT, typename AT>
+hipError_t launch_wide(const KParams& kp, const void* Xv, int64_t ldx, void* Yv, int64_t ldy, int nrhs,
+                       const Timer& tm) {
+    const XT* X = static_cast<const XT*>(Xv);
+    XT* Y = static_cast<XT*>(Yv);
+    // vector loads of X need 16-byte aligned columns: otherwise use the padded copy
+    const bool aligned = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((ldx * int64_t(sizeof(XT))) % 16 == 0);
+    const XT* Xw = X;
+    int64_t ldw = ldx;
+    if (kp.padded || !aligned) {
+        tm.begin(0);
+        hipLaunchKernelGGL((k_padx<XT>), dim3(kp.nleaves), dim3(256), 0, tm.s, kp, X, ldx, nrhs);
+        tm.end(0);
+        Xw = static_cast<const XT*>(kp.xpad);
+        ldw = kp.npad;
+    }
+    if (nrhs <= 16) return launch_wide_nt<XT, AT, 1>(kp, Xw, ldw, Y, ldy, nrhs, tm);
+    if (nrhs <= 32) return launch_wide_nt<XT, AT, 2>(kp, Xw, ldw, Y, ldy, nrhs, tm);
+    if (nrhs <= 64) return launch_wide_nt<XT, AT, 4>(kp, Xw, ldw, Y, ldy, nrhs, tm);
+    return launch_wide_nt<XT, AT, 8>(kp, Xw, ldw, Y, ldy, nrhs, tm);
+}
+
 }  // namespace
 
 int launch_matvec(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs,
                   bool xy_double, bool acc_double, void* stream, void* const* events, bool* ran) {
     const Timer tm{events, ran, static_cast<hipStream_t>(stream)};
     hipError_t e;
-    if (xy_double)
+    if (nrhs >= kWideMin) {
+        if (xy_double)
+            e = acc_double ? launch_wide<double, double>(kp, X, ldx, Y, ldy, nrhs, tm)
+                           : launch_wide<double, float>(kp, X, ldx, Y, ldy, nrhs, tm);
+        else
+            e = acc_double ? launch_wide<float, double>(kp, X, ldx, Y, ldy, nrhs, tm)
+                           : launch_wide<float, float>(kp, X, ldx, Y, ldy, nrhs, tm);
+    } else if (xy_double) {
         e = acc_double ? launch_rg<double, double>(kp, X, ldx, Y, ldy, nrhs, tm)
                        : launch_rg<double, float>(kp, X, ldx, Y, ldy, nrhs, tm);
-    else
+    } else {
         e = acc_double ? launch_rg<float, double>(kp, X, ldx, Y, ldy, nrhs, tm)
                        : launch_rg<float, float>(kp, X, ldx, Y, ldy, nrhs, tm);
+    }
     return int(e);
 }
 

@@ -1,5 +1,9 @@
 """GPU parity: the HIP product against the oracle, through the C ABI.
 
+Products with nrhs >= 16 take the matrix-core path (fp64 MFMA leaf GEMMs,
+fp32/fp64 MFMA low-rank tiles); smaller ones the wave-reduction path.  Both
+are checked here, on the same operators.
+
 Every case compares the library's Y with the oracle's fp64 product of the
 same stored operator (same fp64 factors, same formats, same codes), entry
 by entry, under the componentwise tolerance of ``oracle.bounds.tolerance``
@@ -77,7 +81,7 @@ def test_c1_uniform_fp64_full_size_and_layout():
         assert np.array_equal(vc, Q.quantize(case.op.V[b], "fp64").codes)
 
 
-@pytest.mark.parametrize("nrhs", [1, 2, 3, 8, 17])
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 8, 16, 17, 32, 33, 128])
 def test_c2_small_adaptive(nrhs):
     case = Case("c2_s")
     h = case.library_op()
@@ -97,7 +101,7 @@ def test_forced_format_every_level(fmt):
         uc, ue, vc, ve = h.export_block(b, from_device=True)
         qu = Q.quantize(case.op.U[b], fmt)
         assert np.array_equal(uc, qu.codes) and np.array_equal(ue, qu.exps)
-    for nrhs in (1, 4):
+    for nrhs in (1, 4, 24):
         _run(case, h, [fmt] * case.depth, nrhs, "fp32", "fp32", f"forced-{fmt}")
 
 
@@ -108,8 +112,11 @@ def test_mixed_formats_and_fp64_accumulation():
     h.set_level_precisions(fm, H.ACC_FP64)
     assert h.info()["acc_dtype"] == "fp64"
     _run(case, h, fm, 3, "fp32", "fp64", "mixed-acc64")
+    _run(case, h, fm, 19, "fp32", "fp64", "mixed-acc64-wide")
+    _run(case, h, fm, 16, "fp64", "fp64", "mixed-acc64-xy64-wide")
     h.set_level_precisions(["e5m2", "fp16", "bf16", "fp32", "fp64"])
     _run(case, h, ["e5m2", "fp16", "bf16", "fp32", "fp64"], 2, "fp64", "fp32", "mixed-xy64")
+    _run(case, h, ["e5m2", "fp16", "bf16", "fp32", "fp64"], 40, "fp64", "fp32", "mixed-xy64-wide")
 
 
 @pytest.mark.parametrize("cfg", ["mat1", "mat2", "mat3", "mat4"])
@@ -121,8 +128,12 @@ def test_paper_kernels_padded_leaves(cfg):
     a = case.oracle_assign(case.cfg.allowed)
     assert [lv[0] for lv in h.levels()] == a.fmt
     X, yg, _, _ = _run(case, h, a.fmt, 2, "fp64", h.info()["acc_dtype"], cfg)
+    X2, yg2, _, _ = _run(case, h, a.fmt, 20, "fp64", h.info()["acc_dtype"], cfg + "-wide")
     A = case.cfg.kernel.dense(case.P)
     nA = np.sqrt(case.op.norm2_all)
+    for j in range(20):
+        eta = np.linalg.norm(yg2[:, j] - A @ X2[:, j]) / (nA * np.linalg.norm(X2[:, j]))
+        assert eta <= BD.matvec_backward_bound(case.depth, case.eps)
     for j in range(2):
         eta = np.linalg.norm(yg[:, j] - A @ X[:, j]) / (nA * np.linalg.norm(X[:, j]))
         assert eta <= BD.matvec_backward_bound(case.depth, case.eps)
@@ -133,22 +144,49 @@ def test_edge_cases_depth0_n1_rank0_empty_leaves():
     rng = np.random.default_rng(3)
     D = rng.standard_normal((37, 37))
     h = H.Operator(37, 0, [D], [], [])
-    X = rng.standard_normal((37, 2))
-    yg = _gpu_product(h, X, "fp64")
-    assert np.allclose(yg, D @ X, rtol=0, atol=1e-13 * np.abs(D).sum())
+    for nrhs in (2, 16, 21):
+        X = rng.standard_normal((37, nrhs))
+        yg = _gpu_product(h, X, "fp64")
+        assert np.allclose(yg, D @ X, rtol=0, atol=1e-13 * np.abs(D).sum())
     # n = 1
     h1 = H.Operator(1, 0, [np.array([[2.5]])], [], [])
     assert _gpu_product(h1, np.array([[4.0]]), "fp64")[0, 0] == 10.0
+    assert (_gpu_product(h1, np.full((1, 16), 4.0), "fp64") == 10.0).all()
     # rank-0 blocks everywhere, ragged leaves
     case = Case("c2_s", n=999, depth=3, eps=0.99)
     h2 = case.library_op()
     h2.set_level_precisions(["fp32"] * 3)
     _run(case, h2, ["fp32"] * 3, 1, "fp32", "fp32", "eps0.99")
+    _run(case, h2, ["fp32"] * 3, 17, "fp32", "fp32", "eps0.99-wide")
     # empty leaves (given leaf bounds)
     case3 = Case("c2_s", n=600, depth=2, eps=1e-4, leaf_bounds=[0, 0, 250, 250, 600])
     h3 = case3.library_op()
     h3.set_level_precisions(["fp32", "fp16"])
     _run(case3, h3, ["fp32", "fp16"], 3, "fp32", "fp32", "empty-leaves")
+    _run(case3, h3, ["fp32", "fp16"], 16, "fp32", "fp32", "empty-leaves-wide")
+
+
+@pytest.mark.parametrize("nrhs", [5, 20])
+def test_strided_unaligned_x_and_y(nrhs):
+    """ld of X and Y not a multiple of 4 elements (unpadded operator): the
+    wave path reads X in place, the matrix-core path through its copy."""
+    case = Case("c2_s", n=4096, depth=4, eps=1e-4)
+    h = case.library_op()
+    h.assign_precision(case.eps, case.cfg.allowed, case.norms2)
+    fm = [lv[0] for lv in h.levels()]
+    X = case.cfg.X(nrhs)[:4096]
+    Xb = torch.zeros(nrhs, 4096 + 1, dtype=torch.float32, device=DEV)
+    Xv = Xb[:, :4096].t()
+    Xv.copy_(torch.from_numpy(X).float())
+    Yb = torch.full((nrhs, 4096 + 3), 7.0, dtype=torch.float32, device=DEV)
+    Yv = Yb[:, :4096].t()
+    _say(f"[parity] strided n=4096 nrhs={nrhs} ldx=4097 ldy=4099")
+    h.matvec(Xv, Yv)
+    torch.cuda.synchronize()
+    y, z, _, _ = case.oracle_product(fm, X.astype(np.float32).astype(np.float64))
+    st = check(Yv.cpu().double().numpy(), y, z, case.chain(), "fp32", "fp32", "strided")
+    assert (Yb[:, 4096:] == 7.0).all()       # nothing written past the n rows of each column
+    _say(f"    ok {st}")
 
 
 def test_deterministic_and_stream_safe():
@@ -165,6 +203,15 @@ def test_deterministic_and_stream_safe():
     s.synchronize()
     torch.cuda.synchronize()
     assert torch.equal(y1, y2)
+    X = case.cfg.X(32)[:4096]
+    Xw = H.colmajor_empty(4096, 32, torch.float32, DEV)
+    Xw.copy_(torch.from_numpy(np.asfortranarray(X)).float())
+    w1 = h.matvec(Xw).clone()
+    with torch.cuda.stream(s):
+        w2 = h.matvec(Xw, stream=s)
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(w1, w2)
 
 
 @pytest.mark.slow
