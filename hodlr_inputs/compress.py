@@ -110,10 +110,14 @@ def _random_block(kernel, P, b, eps, rule, norm_a_2, pool, rng, s0):
         nb2 = float(sum(o[1] for o in out))
         Q, _ = np.linalg.qr(Y)
 
-        def p2(t):
-            B = kernel.block(P, r0 + t[0], r0 + t[1], c0, c0 + nc)
-            return Q[t[0]:t[1]].T @ B
-        M = np.sum(pool.map(p2, tiles), axis=0)
+        def p2(group):                   # each worker adds up its own tiles
+            M = np.zeros((Q.shape[1], nc))
+            for t in group:
+                B = kernel.block(P, r0 + t[0], r0 + t[1], c0, c0 + nc)
+                M += Q[t[0]:t[1]].T @ B
+            return M
+        groups = [tiles[w::pool.nw] for w in range(min(pool.nw, len(tiles)))]
+        M = np.sum(pool.map(p2, groups), axis=0)
         if exact_res:
             def p3(t):
                 B = kernel.block(P, r0 + t[0], r0 + t[1], c0, c0 + nc)

@@ -33,7 +33,7 @@ EXPORTS = ("hodlr_depth_for_leaf", "hodlr_tree_bounds", "hodlr_tree_blocks", "ho
            "hodlr_matvec_batched", "hodlr_profile", "hodlr_profile_read", "hodlr_destroy",
            "hodlr_status_string", "hodlr_last_error")
 
-PHASES = ("pad_x", "contract", "expand", "reserved3")
+PHASES = ("pad_x", "contract", "expand", "reduce")
 
 
 class HodlrError(RuntimeError):

@@ -120,6 +120,10 @@ struct KParams {
     int32_t ncitems;
     int32_t netiles;
     int32_t padded;              // 1 if any leaf has padding rows (X goes through xpad)
+    int32_t max_block_rank;      // largest rank of a block
+    int32_t max_tstage;          // matrix-core expansion: largest sum, over one leaf's ancestor
+                                 // blocks, of round_up(rank, 32) * (8 if fp64 else 4) bytes
+                                 // (T of every level staged in LDS, per right-hand side)
 };
 
 // Counters of the contraction launch: kSyncHead reserved words, then one
@@ -127,7 +131,7 @@ struct KParams {
 constexpr int kSyncHead = 4;
 constexpr int64_t sync_words(int64_t nblocks) { return kSyncHead + nblocks; }
 
-constexpr int kPhases = 4;     // padded X copy, contraction, expansion, (reserved)
+constexpr int kPhases = 4;     // padded X copy, contraction, expansion, reduction of partials
 
 // Launch the whole product on `stream`.  xy_double: X/Y are fp64 (else fp32);
 // acc_double: accumulation precision of Y.  events: NULL, or 2 * kPhases

@@ -260,6 +260,8 @@ struct hodlr_op_s {
     int64_t scaled_cols = 0;
     int32_t max_leaf = 0;
     int32_t max_rank_path = 0;
+    int32_t max_tstage = 0;      // see KParams::max_tstage
+    int32_t max_block_rank = 0;
     int32_t max_items_rank = 0;
 
     // device
@@ -512,6 +514,18 @@ hodlr_status pack(hodlr_op_s* op) {
         int32_t sum = 0;
         for (int k = 1; k <= op->depth; ++k) sum += op->rank[((1 << k) - 2) + (i >> (op->depth - k))];
         op->max_rank_path = std::max(op->max_rank_path, sum);
+    }
+    op->max_block_rank = 0;
+    for (int b = 0; b < nb; ++b) op->max_block_rank = std::max(op->max_block_rank, op->rank[b]);
+    op->max_tstage = 0;
+    for (int i = 0; i < op->nleaves; ++i) {
+        int32_t bytes = 0;
+        for (int k = 1; k <= op->depth; ++k) {
+            const int b = ((1 << k) - 2) + (i >> (op->depth - k));
+            const int32_t w = (op->acc_double || op->bdesc[b].fmt == F64) ? 8 : 4;
+            bytes += ((op->rank[b] + 31) / 32) * 32 * w;
+        }
+        op->max_tstage = std::max(op->max_tstage, bytes);
     }
 
     std::vector<uint8_t> img;
@@ -1032,6 +1046,8 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
     kp->npad = op->npad;
     kp->max_leaf = op->max_leaf;
     kp->max_rank_path = op->max_rank_path;
+    kp->max_tstage = op->max_tstage;
+    kp->max_block_rank = op->max_block_rank;
     kp->max_items_rank = op->max_items_rank;
     kp->depth = op->depth;
     kp->nblocks = op->nb;

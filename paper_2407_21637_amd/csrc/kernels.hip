@@ -772,7 +772,8 @@ __device__ __forceinline__ void load_x8(const XT* p, CT v[kKL]) {
 // Contraction item on the matrix cores: partial T_b over rows [r0, r0+nr)
 // of the V panel for right-hand sides [c0, c0 + 16 NT).  The waves split
 // the rows in 32-row steps; each keeps a (16 PG) x (16 NT) block of partial
-// sums per pass over the rank and the four are added in LDS (`red`).
+// sums per pass over the rank and the four are added in LDS (`red`).  The
+// partials are summed over items by k_reduce_w after the launch.
 template <int F, typename CT, typename XT, int NT>
 __device__ void contract_item_w(const KParams& kp, const CItem& it, const BlockDesc& bd,
                                 const XT* __restrict__ X, int64_t ldx, int nrhs, int c0, CT* red) {
@@ -839,7 +840,7 @@ __device__ void contract_item_w(const KParams& kp, const CItem& it, const BlockD
                 CT s = CT(0);
 #pragma unroll
                 for (int w = 0; w < kWaves; ++w) s += red[(w * NT) * 256 + idx];
-                if (j < p && c < nrhs) st_coh(part + int64_t(c) * p + j, double(s));
+                if (j < p && c < nrhs) part[int64_t(c) * p + j] = double(s);
             }
             __syncthreads();
         }
@@ -848,9 +849,8 @@ __device__ void contract_item_w(const KParams& kp, const CItem& it, const BlockD
 
 template <typename XT, typename AT, int NT>
 __global__ __launch_bounds__(kThreads) void k_contract_w(KParams kp, const XT* __restrict__ Xc, int64_t ldc,
-                                                         int nrhs, int stage_cap) {
+                                                         int nrhs) {
     extern __shared__ double smem_d[];
-    __shared__ int s_flag;
     const CItem it = kp.citems[blockIdx.x];
     const BlockDesc bd = kp.blocks[it.block];
     const int c0 = blockIdx.y * 16 * NT;
@@ -862,27 +862,60 @@ __global__ __launch_bounds__(kThreads) void k_contract_w(KParams kp, const XT* _
         case E4M3: contract_item_w<E4M3, AT, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<AT*>(smem_d)); break;
         default: contract_item_w<E5M2, AT, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<AT*>(smem_d)); break;
     }
-    // every (item, right-hand-side group) workgroup of the block counts once
-    drain_and_sync();
-    if (threadIdx.x == 0)
-        s_flag = (add_coh(arrivals(kp) + it.block, 1) == bd.nitems * int(gridDim.y) - 1);
-    __syncthreads();
-    if (s_flag) {
-        double* stage = smem_d;
-        if (bd.fmt == F64)
-            finish_block<double>(kp, bd, nrhs, stage, stage_cap);
-        else
-            finish_block<AT>(kp, bd, nrhs, stage, stage_cap);
-        if (threadIdx.x == 0) st_coh(arrivals(kp) + it.block, 0);
+}
+
+// T_b = tscale .* (sum of the block's item partials, in item order): one
+// thread per output (j, c) of block blockIdx.x, 256 outputs per workgroup
+// along blockIdx.y.  fp64 blocks add in fp64, others in the accumulation type.
+template <typename CT>
+__device__ void reduce_block(const KParams& kp, const BlockDesc& bd, int o, int total) {
+    const double* src = kp.partial + kp.citems[bd.item0].poff * (total / bd.rank) + o;
+    CT s = CT(0);
+    int c = 0;
+    for (; c + 8 <= bd.nitems; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = src[int64_t(c + q) * total];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s += CT(v[q]);
+    }
+    for (; c < bd.nitems; ++c) s += CT(src[int64_t(c) * total]);
+    kp.T[bd.t_off * (total / bd.rank) + o] = double(s) * kp.tscale[bd.ts_off + o % bd.rank];
+}
+
+template <typename AT>
+__global__ __launch_bounds__(256) void k_reduce_w(KParams kp, int nrhs) {
+    const BlockDesc bd = kp.blocks[blockIdx.x];
+    const int total = bd.rank * nrhs;
+    const int o = blockIdx.y * 256 + threadIdx.x;
+    if (o >= total) return;
+    if (bd.fmt == F64)
+        reduce_block<double>(kp, bd, o, total);
+    else
+        reduce_block<AT>(kp, bd, o, total);
+}
+
+// rows [j0, j0 + rows) of T_b for right-hand sides [c0, c0 + CW), zero
+// beyond the rank or nrhs, as ts[j][c]
+template <typename CT, int CW>
+__device__ __forceinline__ void stage_t(const KParams& kp, const BlockDesc& bd, int j0, int rows, int c0, int nrhs,
+                                        CT* ts) {
+    const int p = bd.rank;
+    const double* Tb = kp.T + bd.t_off * nrhs;
+    for (int idx = threadIdx.x; idx < rows * CW; idx += kThreads) {
+        const int jr = idx / CW, cl = idx - jr * CW;
+        const int j = j0 + jr, c = c0 + cl;
+        ts[idx] = (j < p && c < nrhs) ? CT(Tb[int64_t(c) * p + j]) : CT(0);
     }
 }
 
 // One level's U_b T_b added to a wave's two 16-row tiles (accumulators in
-// the fp64 row layout).  T_b is staged in LDS kJC rows at a time as
-// ts[j][c]; rows j >= p are zero.
+// the fp64 row layout).  T_b comes from LDS as ts[j][c]: either staged
+// whole before the call (`staged`, round_up(p, 32) rows), or here, kJC rows
+// at a time; rows j >= p are zero.
 template <int F, typename CT, int NT>
 __device__ void expand_level_w(const KParams& kp, const BlockDesc& bd, int chunk0, int ld, int c0, int nrhs,
-                               bool act0, bool act1, CT* ts, typename Mfma<CT>::acc_t acc[2][NT]) {
+                               bool act0, bool act1, CT* ts, bool staged, typename Mfma<CT>::acc_t acc[2][NT]) {
     using M = Mfma<CT>;
     constexpr int S = Codec<F>::kBytes;
     constexpr int CW = 16 * NT;
@@ -890,17 +923,15 @@ __device__ void expand_level_w(const KParams& kp, const BlockDesc& bd, int chunk
     const int li = lane & 15, g = lane >> 4;
     const int p = bd.rank;
     const uint8_t* Up = kp.fac + bd.u_off + int64_t(chunk0) * p * S;
-    const double* Tb = kp.T + bd.t_off * nrhs;
     // fp32 results are steered into the fp64 row layout of the accumulators
     const int r0 = 32 * wave + (sizeof(CT) == 8 ? li : f64_layout_row(li)), r1 = r0 + 16;
     for (int j0 = 0; j0 < p; j0 += kJC) {
-        __syncthreads();                                // previous users of ts are done
-        for (int idx = threadIdx.x; idx < kJC * CW; idx += kThreads) {
-            const int jr = idx / CW, cl = idx - jr * CW;
-            const int j = j0 + jr, c = c0 + cl;
-            ts[idx] = (j < p && c < nrhs) ? CT(Tb[int64_t(c) * p + j]) : CT(0);
+        const CT* tj = ts + (staged ? j0 * CW : 0);
+        if (!staged) {
+            __syncthreads();                            // previous users of ts are done
+            stage_t<CT, CW>(kp, bd, j0, kJC, c0, nrhs, ts);
+            __syncthreads();
         }
-        __syncthreads();
         CT a0[kKL], a1[kKL];
 #pragma unroll
         for (int q = 0; q < kKL; ++q) {
@@ -917,7 +948,7 @@ __device__ void expand_level_w(const KParams& kp, const BlockDesc& bd, int chunk
         for (int q = 0; q < kKL; ++q)
 #pragma unroll
             for (int ct = 0; ct < NT; ++ct) {
-                const CT bv = ts[(g * kKL + q) * CW + 16 * ct + li];
+                const CT bv = tj[(g * kKL + q) * CW + 16 * ct + li];
                 acc[0][ct] = M::mma(a0[q], bv, acc[0][ct]);
                 acc[1][ct] = M::mma(a1[q], bv, acc[1][ct]);
             }
@@ -926,90 +957,157 @@ __device__ void expand_level_w(const KParams& kp, const BlockDesc& bd, int chunk
 
 template <typename CT, int NT>
 __device__ void expand_level_dispatch(const KParams& kp, const BlockDesc& bd, int chunk0, int ld, int c0, int nrhs,
-                                      bool act0, bool act1, CT* ts, typename Mfma<CT>::acc_t acc[2][NT]) {
+                                      bool act0, bool act1, CT* ts, bool staged,
+                                      typename Mfma<CT>::acc_t acc[2][NT]) {
     switch (bd.fmt) {
-        case F64: expand_level_w<F64, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, acc); break;
-        case F32: expand_level_w<F32, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, acc); break;
-        case BF16: expand_level_w<BF16, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, acc); break;
-        case F16: expand_level_w<F16, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, acc); break;
-        case E4M3: expand_level_w<E4M3, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, acc); break;
-        default: expand_level_w<E5M2, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, acc); break;
+        case F64: expand_level_w<F64, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, staged, acc); break;
+        case F32: expand_level_w<F32, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, staged, acc); break;
+        case BF16: expand_level_w<BF16, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, staged, acc); break;
+        case F16: expand_level_w<F16, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, staged, acc); break;
+        case E4M3: expand_level_w<E4M3, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, staged, acc); break;
+        default: expand_level_w<E5M2, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, staged, acc); break;
     }
 }
+
+// a 32-row step of the leaf GEMM: the lane's D values (two 16-row tiles)
+// and its kKL rows of X for each column tile
+template <typename XT, int NT>
+struct LeafStep {
+    double a0[kKL], a1[kKL];
+    XT b[NT][kKL];
+    __device__ __forceinline__ void load(const double* Dp, int nr, const XT* Xl, int64_t ldw, int k, bool ok,
+                                         bool act0, bool act1, int r0, int r1, int c0, int li, int nrhs) {
+#pragma unroll
+        for (int q = 0; q < kKL; ++q) {
+            a0[q] = (ok && act0) ? Dp[int64_t(k + q) * nr + r0] : 0.0;
+            a1[q] = (ok && act1) ? Dp[int64_t(k + q) * nr + r1] : 0.0;
+        }
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+            const int c = c0 + 16 * ct + li;
+            if (ok && c < nrhs)
+                load_x8<XT, XT>(Xl + k + ldw * c, b[ct]);
+            else
+#pragma unroll
+                for (int q = 0; q < kKL; ++q) b[ct][q] = XT(0);
+        }
+    }
+    __device__ __forceinline__ void mma(typename Mfma<double>::acc_t acc[2][NT]) const {
+#pragma unroll
+        for (int q = 0; q < kKL; ++q)
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+                acc[0][ct] = Mfma<double>::mma(a0[q], double(b[ct][q]), acc[0][ct]);
+                acc[1][ct] = Mfma<double>::mma(a1[q], double(b[ct][q]), acc[1][ct]);
+            }
+    }
+};
 
 // Expansion tile on the matrix cores: rows [r0, r0+nr) of leaf i (at most
 // 128, a multiple of 16) for right-hand sides [c0, c0 + 16 NT).  Wave w
 // owns tile rows 32w..32w+31 as two 16-row MFMA tiles.  The fp64 leaf GEMM
 // and every fp64 level accumulate in fp64; levels decoded to fp32 (when AT
-// is float) accumulate in fp32; the sum is rounded once into Y.
+// is float) accumulate in fp32; the sum is rounded once into Y.  When the
+// T of all the leaf's levels fits in the LDS given (lds_bytes), it is
+// staged once, before the leaf GEMM, and the levels need no barrier.
 template <typename XT, typename AT, int NT>
 __global__ __launch_bounds__(kThreads) void k_expand_w(KParams kp, const XT* __restrict__ Xw, int64_t ldw,
-                                                       XT* __restrict__ Y, int64_t ldy, int nrhs) {
+                                                       XT* __restrict__ Y, int64_t ldy, int nrhs, int lds_bytes) {
     extern __shared__ double smem_d[];
+    __shared__ int s_off[kMaxDepth + 2];
     using MD = Mfma<double>;
+    constexpr int CW = 16 * NT;
     const ETile t = kp.etiles[blockIdx.x];
     const LeafDesc L = kp.leaves[t.leaf];
-    const int c0 = blockIdx.y * 16 * NT;
+    const int c0 = blockIdx.y * CW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, g = lane >> 4;
     const int r0 = 32 * wave + li, r1 = r0 + 16;        // tile rows of the lane's A operands
     const bool act0 = 32 * wave < t.nr, act1 = 32 * wave + 16 < t.nr;   // nr is a multiple of 16
+    const int depth = kp.depth;
+    // byte offsets of each level's staged T in LDS (level k at s_off[k-1])
+    if (threadIdx.x < depth) {
+        const int k = threadIdx.x + 1;
+        const BlockDesc& bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
+        const int w = (sizeof(AT) == 8 || bd.fmt == F64) ? 8 : 4;
+        s_off[k] = ((bd.rank + kJC - 1) / kJC) * kJC * CW * w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int off = 0;
+        for (int k = 1; k <= depth; ++k) {
+            const int sz = s_off[k];
+            s_off[k - 1] = off;
+            off += sz;
+        }
+        s_off[depth] = off;
+    }
+    __syncthreads();
+    const bool staged = s_off[depth] <= lds_bytes;
+    unsigned char* lds = reinterpret_cast<unsigned char*>(smem_d);
+    if (staged) {
+        for (int k = 1; k <= depth; ++k) {
+            const BlockDesc& bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
+            const int rows = ((bd.rank + kJC - 1) / kJC) * kJC;
+            if (sizeof(AT) == 8 || bd.fmt == F64)
+                stage_t<double, CW>(kp, bd, 0, rows, c0, nrhs, reinterpret_cast<double*>(lds + s_off[k - 1]));
+            else
+                stage_t<float, CW>(kp, bd, 0, rows, c0, nrhs, reinterpret_cast<float*>(lds + s_off[k - 1]));
+        }
+    }
     MD::acc_t accd[2][NT];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < NT; ++b) zero_acc(accd[a][b]);
-    // leaf: D_i (tile rows, all mp columns; column-major, ld = nr) times X_i
+    // leaf: D_i (tile rows, all mp columns; column-major, ld = nr) times X_i,
+    // two steps in flight
     {
         const double* Dp = kp.leafd + L.d_off + int64_t(t.r0) * L.mp;
         const XT* Xl = Xw + L.prow0;
-        for (int k0 = 0; k0 < L.mp; k0 += kStep) {
-            const int k = k0 + g * kKL;                 // mp and k are multiples of 8
-            const bool ok = k < L.mp;
-            double a0[kKL], a1[kKL];
-            XT b[NT][kKL];
-#pragma unroll
-            for (int q = 0; q < kKL; ++q) {
-                a0[q] = (ok && act0) ? Dp[int64_t(k + q) * t.nr + r0] : 0.0;
-                a1[q] = (ok && act1) ? Dp[int64_t(k + q) * t.nr + r1] : 0.0;
+        if constexpr (NT >= 8) {                        // 128 columns: one step at a time (registers)
+            LeafStep<XT, NT> sa;
+            for (int k0 = 0; k0 < L.mp; k0 += kStep) {
+                const int k = k0 + g * kKL;
+                sa.load(Dp, t.nr, Xl, ldw, k, k < L.mp, act0, act1, r0, r1, c0, li, nrhs);
+                sa.mma(accd);
             }
-#pragma unroll
-            for (int ct = 0; ct < NT; ++ct) {
-                const int c = c0 + 16 * ct + li;
-                if (ok && c < nrhs)
-                    load_x8<XT, XT>(Xl + k + ldw * c, b[ct]);
-                else
-#pragma unroll
-                    for (int q = 0; q < kKL; ++q) b[ct][q] = XT(0);
+        } else {
+            LeafStep<XT, NT> sa, sb;
+            sa.load(Dp, t.nr, Xl, ldw, g * kKL, g * kKL < L.mp, act0, act1, r0, r1, c0, li, nrhs);
+            for (int k0 = 0; k0 < L.mp; k0 += 2 * kStep) {
+                const int kb = k0 + kStep + g * kKL;     // mp and k are multiples of 8
+                sb.load(Dp, t.nr, Xl, ldw, kb, kb < L.mp, act0, act1, r0, r1, c0, li, nrhs);
+                sa.mma(accd);
+                if (k0 + kStep >= L.mp) break;
+                const int ka = k0 + 2 * kStep + g * kKL;
+                sa.load(Dp, t.nr, Xl, ldw, ka, ka < L.mp, act0, act1, r0, r1, c0, li, nrhs);
+                sb.mma(accd);
             }
-#pragma unroll
-            for (int q = 0; q < kKL; ++q)
-#pragma unroll
-                for (int ct = 0; ct < NT; ++ct) {
-                    accd[0][ct] = MD::mma(a0[q], double(b[ct][q]), accd[0][ct]);
-                    accd[1][ct] = MD::mma(a1[q], double(b[ct][q]), accd[1][ct]);
-                }
         }
     }
+    if (staged) __syncthreads();                        // T of every level is in LDS
     // the depth ancestors' blocks whose rows contain this leaf
     typename Mfma<AT>::acc_t accl[2][NT];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < NT; ++b) zero_acc(accl[a][b]);
-    const int depth = kp.depth;
     for (int k = 1; k <= depth; ++k) {
         const BlockDesc bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
         if (bd.rank == 0) continue;
         const int chunk0 = L.prow0 - bd.urow0 + t.r0;   // the tile's chunk of the U panel
+        unsigned char* ts = lds + (staged ? s_off[k - 1] : 0);
         if constexpr (sizeof(AT) == 8) {
-            expand_level_dispatch<double, NT>(kp, bd, chunk0, t.nr, c0, nrhs, act0, act1, smem_d, accd);
+            expand_level_dispatch<double, NT>(kp, bd, chunk0, t.nr, c0, nrhs, act0, act1,
+                                              reinterpret_cast<double*>(ts), staged, accd);
         } else {
             if (bd.fmt == F64)
-                expand_level_dispatch<double, NT>(kp, bd, chunk0, t.nr, c0, nrhs, act0, act1, smem_d, accd);
+                expand_level_dispatch<double, NT>(kp, bd, chunk0, t.nr, c0, nrhs, act0, act1,
+                                                  reinterpret_cast<double*>(ts), staged, accd);
             else
                 expand_level_dispatch<float, NT>(kp, bd, chunk0, t.nr, c0, nrhs, act0, act1,
-                                                 reinterpret_cast<float*>(smem_d), accl);
+                                                 reinterpret_cast<float*>(ts), staged, accl);
         }
     }
     // Y rows g+4e of each 16-row tile (fp64 layout), column li of each column tile
@@ -1030,28 +1128,30 @@ __global__ __launch_bounds__(kThreads) void k_expand_w(KParams kp, const XT* __r
     }
 }
 
-size_t lds_contract_w(const KParams& kp, int nt, size_t acc_bytes, int sc) {
-    const size_t red = size_t(kWaves) * nt * 256 * acc_bytes;
-    const size_t stage = size_t(sc) * 8;
-    return red > stage ? red : stage;
-}
-
 template <typename XT, typename AT, int NT>
 hipError_t launch_wide_nt(const KParams& kp, const XT* Xw, int64_t ldw, XT* Y, int64_t ldy, int nrhs,
                           const Timer& tm) {
     hipStream_t s = tm.s;
     constexpr int NTC = NT > 4 ? 4 : NT;                // contraction: at most 64 columns per workgroup
+    constexpr int CW = 16 * NT;
     if (kp.ncitems > 0) {
-        const int sc = stage_cap(kp, 8);
-        const size_t acc_bytes = sizeof(double);        // fp64 levels use the same buffer
         tm.begin(1);
         hipLaunchKernelGGL((k_contract_w<XT, AT, NTC>), dim3(kp.ncitems, (nrhs + 16 * NTC - 1) / (16 * NTC)),
-                           dim3(kThreads), lds_contract_w(kp, NTC, acc_bytes, sc), s, kp, Xw, ldw, nrhs, sc);
+                           dim3(kThreads), size_t(kWaves) * NTC * 256 * sizeof(double), s, kp, Xw, ldw, nrhs);
         tm.end(1);
+        // largest rank * nrhs of a block bounds the outputs per block
+        tm.begin(3);
+        const int64_t rows_y = (int64_t(kp.max_block_rank) * nrhs + 255) / 256;
+        hipLaunchKernelGGL((k_reduce_w<AT>), dim3(kp.nblocks, unsigned(rows_y)), dim3(256), 0, s, kp, nrhs);
+        tm.end(3);
     }
+    // LDS: T of all levels when it fits in 64 KB, else kJC rows at a time
+    const int64_t all = int64_t(kp.max_tstage) * CW;
+    const int64_t chunk = int64_t(kJC) * CW * 8;
+    const int64_t lds = all <= kMaxLds ? (all > chunk ? all : chunk) : chunk;
     tm.begin(2);
-    hipLaunchKernelGGL((k_expand_w<XT, AT, NT>), dim3(kp.netiles, (nrhs + 16 * NT - 1) / (16 * NT)), dim3(kThreads),
-                       size_t(kJC) * 16 * NT * sizeof(double), s, kp, Xw, ldw, Y, ldy, nrhs);
+    hipLaunchKernelGGL((k_expand_w<XT, AT, NT>), dim3(kp.netiles, (nrhs + CW - 1) / CW), dim3(kThreads),
+                       size_t(lds), s, kp, Xw, ldw, Y, ldy, nrhs, int(lds));
     tm.end(2);
     return hipGetLastError();
 }
