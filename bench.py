@@ -85,7 +85,8 @@ SBYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2, "e4m3": 1, "e5m2": 1}
 
 
 def work(h, n, nrhs, xy_bytes):
-    """Algorithmic bytes and flops of one product, and per kernel."""
+    """Algorithmic bytes and flops of one product; bytes of the expansion and
+    contraction launches; fp64 flops of the leaf products."""
     inf = h.info()
     B = inf["leaf_bytes"] + inf["factor_bytes"] + inf["scale_bytes"] + n * nrhs * 2 * xy_bytes
     lr = ub = vb = 0
@@ -98,7 +99,8 @@ def work(h, n, nrhs, xy_bytes):
     F = 2 * nrhs * (inf["leaf_bytes"] // 8 + lr)
     expand = inf["leaf_bytes"] + ub + n * nrhs * 2 * xy_bytes
     contract = vb + n * nrhs * xy_bytes
-    return B, F, expand, contract
+    leaf_flops = 2 * nrhs * (inf["leaf_bytes"] // 8)
+    return B, F, expand, contract, leaf_flops
 
 
 def time_steps(h, X, Y, steps, warmup, torch):
@@ -190,7 +192,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=None, help="default: the workload's first nrhs")
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-run", action="store_true",
@@ -221,53 +223,68 @@ def main():
     H.lib()   # fail loudly if the HIP library is not built
     dev = torch.device("cuda:0")
     cfg = CF.get(args.workload)
+    nrhs0 = args.nrhs if args.nrhs is not None else cfg.nrhs[0]
     P, blocks, leaves, op = build_operator(cfg, H)
     norms2 = np.concatenate([[op.norm2_all], op.norm2_blocks])
     t = time.time()
     h = H.Operator(cfg.n, cfg.depth, op.leaves, op.U, op.V, device=0)
     h.assign_precision(cfg.eps, cfg.allowed, norms2)
     fmts = [lv[0] for lv in h.levels()]
-    log(f"[bench] operator on GPU in {time.time() - t:.1f}s; formats {fmts}; acc {h.info()['acc_dtype']}")
+    acc = h.info()["acc_dtype"]
+    log(f"[bench] operator on GPU in {time.time() - t:.1f}s; formats {fmts}; acc {acc}")
 
     xdt = torch.float32 if cfg.x_dtype == "fp32" else torch.float64
     xb = 4 if cfg.x_dtype == "fp32" else 8
-    Xh = cfg.X(max(args.nrhs, 32))
+    nrhs_list = [nrhs0] if args.profile_run else [nrhs0] + [k for k in cfg.nrhs if k != nrhs0]
+    Xh = cfg.X(max(nrhs_list))
     results = {}
-    nrhs_list = [args.nrhs] if args.profile_run else sorted({args.nrhs, 32})
     for nrhs in nrhs_list:
         X = H.colmajor_empty(cfg.n, nrhs, xdt, dev)
         X.copy_(torch.from_numpy(np.asfortranarray(Xh[:, :nrhs])).to(xdt))
         Y = H.colmajor_empty(cfg.n, nrhs, xdt, dev)
-        B, Fl, EB, CB = work(h, cfg.n, nrhs, xb)
+        B, Fl, EB, CB, LF = work(h, cfg.n, nrhs, xb)
         ms = time_steps(h, X, Y, args.steps, args.warmup, torch)
         ph = time_phases(h, X, Y, 50, torch)
         cold = time_cold(h, X, Y, 10, torch)
-        results[nrhs] = dict(ms=ms, phases=ph, B=B, F=Fl, EB=EB, CB=CB, cold_ms=cold, X=X, Y=Y)
-        log(f"[bench] nrhs={nrhs}: {ms * 1e3:.1f} us/step, {B / ms / 1e6:.1f} GB/s, cold {cold * 1e3:.1f} us, "
-            f"kernels (us) {ph}")
+        results[nrhs] = dict(ms=ms, phases=ph, B=B, F=Fl, EB=EB, CB=CB, LF=LF, cold_ms=cold, X=X, Y=Y)
+        log(f"[bench] nrhs={nrhs}: {ms * 1e3:.1f} us/step, {B / ms / 1e6:.1f} GB/s, {Fl / ms / 1e9:.2f} Tflop/s, "
+            f"cold {cold * 1e3:.1f} us, kernels (us) {ph}")
     if args.profile_run:
-        print(json.dumps({"profile_run": True, "us_per_step": results[args.nrhs]["ms"] * 1e3}), flush=True)
+        print(json.dumps({"profile_run": True, "us_per_step": results[nrhs0]["ms"] * 1e3}), flush=True)
         return
 
     # uniform-fp64 product on the same GPU, same ranks
+    r = results[nrhs0]
     h.set_level_precisions(["fp64"] * cfg.depth, H.ACC_FP64)
-    r0 = results[args.nrhs]
-    ms64 = time_steps(h, r0["X"], r0["Y"], args.steps, args.warmup, torch)
-    B64 = work(h, cfg.n, args.nrhs, xb)[0]
+    ms64 = time_steps(h, r["X"], r["Y"], args.steps, args.warmup, torch)
+    B64 = work(h, cfg.n, nrhs0, xb)[0]
     h.assign_precision(cfg.eps, cfg.allowed, norms2)
     log(f"[bench] uniform fp64: {ms64 * 1e3:.1f} us/step")
 
-    r = results[args.nrhs]
     exp_us = r["phases"]["expand"]
     con_us = r["phases"].get("contract", 0.0)
-    achieved = r["EB"] / (exp_us * 1e-6) / 1e9
     traffic = traffic_c = None
     tr = read_traffic()
     if tr.get("kernel_sha") == kernel_hash() and tr.get("workload") == cfg.name and \
-            tr.get("nrhs") == str(args.nrhs) and "k_expand_bytes_per_launch" in tr:
+            tr.get("nrhs") == str(nrhs0) and "k_expand_bytes_per_launch" in tr:
         traffic = int(tr["k_expand_bytes_per_launch"])
         traffic_c = int(tr.get("k_contract_bytes_per_launch", 0)) or None
     value = r["B"] / (r["ms"] * 1e-3) / 1e9
+    wide = nrhs0 >= 16
+    exp_gbs = r["EB"] / (exp_us * 1e-6) / 1e9
+    if wide:
+        # matrix-core path: the fp64 leaf GEMM dominates the expansion's work
+        achieved = r["LF"] / (exp_us * 1e-6) / 1e12
+        roof = {"bound": "mfma", "kernel": "k_expand_w (fp64 MFMA leaf GEMM + low-rank MFMA, writes Y)",
+                "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
+                "alg_flops_per_launch": int(r["LF"]), "alg_bytes_per_launch": int(r["EB"]),
+                "hbm_gbs": round(exp_gbs, 2), "mean_launch_us": round(exp_us, 2)}
+    else:
+        roof = {"bound": "hbm", "kernel": "k_expand (fp64 leaf GEMV + expansion, writes Y)",
+                "achieved": round(exp_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(exp_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "alg_bytes_per_launch": int(r["EB"]), "mean_launch_us": round(exp_us, 2)}
     out = {
         "metric": "HODLR matvec GB/s & Gflop/s (% roofline); speedup mixed vs FP64 at fixed eps",
         "value": round(value, 2),
@@ -279,12 +296,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32+f64" if xb == 4 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: {cfg.description}; n={cfg.n}, leaf {cfg.n >> cfg.depth}, "
-                               f"depth {cfg.depth}, eps={cfg.eps:g}, formats {fmts}, fp32 X nrhs={args.nrhs}",
-                   "n": cfg.n, "depth": cfg.depth, "eps": cfg.eps, "nrhs": args.nrhs, "formats": fmts,
-                   "accumulation": h.info()["acc_dtype"]},
+        "config": {"workload": f"{cfg.name}: {cfg.description}; n={cfg.n}, leaf {-(-cfg.n >> cfg.depth)}, "
+                               f"depth {cfg.depth}, eps={cfg.eps:g}, formats {fmts}, {cfg.x_dtype} X nrhs={nrhs0}",
+                   "n": cfg.n, "depth": cfg.depth, "eps": cfg.eps, "nrhs": nrhs0, "formats": fmts,
+                   "accumulation": acc},
         "gflops": round(r["F"] / (r["ms"] * 1e-3) / 1e9, 2),
         "hbm_frac": round(value / HBM_PEAK_GBS, 4),
         "alg_bytes": int(r["B"]),
@@ -293,22 +310,21 @@ def main():
         "speedup_vs_fp64": round(ms64 / r["ms"], 3),
         "fp64_gbs": round(B64 / (ms64 * 1e-3) / 1e9, 2),
         "kernels_us": {k: round(v, 2) for k, v in r["phases"].items()},
-        "roofline": {"bound": "hbm", "kernel": "k_expand (fp64 leaf GEMV + expansion, writes Y)",
-                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "alg_bytes_per_launch": int(r["EB"]), "mean_launch_us": round(exp_us, 2)},
+        "roofline": roof,
         "contract_kernel": {"alg_bytes_per_launch": int(r["CB"]), "mean_launch_us": round(con_us, 2),
                             "achieved_gbs": round(r["CB"] / (con_us * 1e-6) / 1e9, 2) if con_us else None,
                             "traffic": traffic_c},
     }
-    if 32 in results and args.nrhs != 32:
-        r32 = results[32]
-        out["nrhs32"] = {"gbs": round(r32["B"] / (r32["ms"] * 1e-3) / 1e9, 2),
-                         "gflops": round(r32["F"] / (r32["ms"] * 1e-3) / 1e9, 2),
-                         "ms_per_step": round(r32["ms"], 5),
-                         "kernels_us": {k: round(v, 2) for k, v in r32["phases"].items()}}
+    for k in nrhs_list[1:]:
+        rk = results[k]
+        out[f"nrhs{k}"] = {"gbs": round(rk["B"] / (rk["ms"] * 1e-3) / 1e9, 2),
+                           "gflops": round(rk["F"] / (rk["ms"] * 1e-3) / 1e9, 2),
+                           "ms_per_step": round(rk["ms"], 5),
+                           "kernels_us": {q: round(v, 2) for q, v in rk["phases"].items()}}
+        if k >= 16 and "expand" in rk["phases"]:
+            out[f"nrhs{k}"]["leaf_fp64_mfma_tflops"] = round(rk["LF"] / (rk["phases"]["expand"] * 1e-6) / 1e12, 3)
     if not args.no_cpu:
-        Xc = Xh[:, :args.nrhs]
+        Xc = Xh[:, :nrhs0]
         cb, y_ora, U, V, oblocks, lb = cpu_baseline(cfg, blocks, leaves, op, fmts, r["B"], Xc)
         out["cpu_baseline"] = cb
         # accuracy of the timed product against the oracle
@@ -319,7 +335,7 @@ def main():
         yg = r["Y"].cpu().double().numpy()
         z = MV.matvec_abs(cfg.n, oblocks, lb, op.leaves, U, V, Xc)
         M = BD.chain_length(oblocks, op.ranks, [m for _, m in lb], cfg.depth)
-        u_acc = 2.0 ** -24 if h.info()["acc_dtype"] == "fp32" else 2.0 ** -53
+        u_acc = 2.0 ** -24 if acc == "fp32" else 2.0 ** -53
         tau = BD.tolerance_prob(z, y_ora, M, u_acc, 2.0 ** -24 if xb == 4 else 2.0 ** -53)
         err = np.abs(yg - y_ora)
         out["check"] = {"max_err_over_tau_prob": float((err / tau).max()),

@@ -122,8 +122,8 @@ struct KParams {
     int32_t padded;              // 1 if any leaf has padding rows (X goes through xpad)
     int32_t max_block_rank;      // largest rank of a block
     int32_t max_tstage;          // matrix-core expansion: largest sum, over one leaf's ancestor
-                                 // blocks, of round_up(rank, 32) * (8 if fp64 else 4) bytes
-                                 // (T of every level staged in LDS, per right-hand side)
+                                 // blocks, of round_up(rank, 4) * (8 if fp64 else 4) bytes
+                                 // (T of every level staged in LDS, per LDS row element)
 };
 
 // Counters of the contraction launch: kSyncHead reserved words, then one

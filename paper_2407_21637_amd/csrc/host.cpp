@@ -523,7 +523,7 @@ hodlr_status pack(hodlr_op_s* op) {
         for (int k = 1; k <= op->depth; ++k) {
             const int b = ((1 << k) - 2) + (i >> (op->depth - k));
             const int32_t w = (op->acc_double || op->bdesc[b].fmt == F64) ? 8 : 4;
-            bytes += ((op->rank[b] + 31) / 32) * 32 * w;
+            bytes += ((op->rank[b] + 3) / 4) * 4 * w;
         }
         op->max_tstage = std::max(op->max_tstage, bytes);
     }

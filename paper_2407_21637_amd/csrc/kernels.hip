@@ -705,7 +705,6 @@ hipError_t launch_rg(const KParams& kp, const void* X, int64_t ldx, void* Y, int
 constexpr int kWideMin = 16;
 constexpr int kKL = 8;                      // consecutive rows per lane per step
 constexpr int kStep = 4 * kKL;              // rows per MFMA step (4 lane groups)
-constexpr int kJC = 32;                     // T rows staged in LDS at a time
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -773,7 +772,8 @@ __device__ __forceinline__ void load_x8(const XT* p, CT v[kKL]) {
 // of the V panel for right-hand sides [c0, c0 + 16 NT).  The waves split
 // the rows in 32-row steps; each keeps a (16 PG) x (16 NT) block of partial
 // sums per pass over the rank and the four are added in LDS (`red`).  The
-// partials are summed over items by k_reduce_w after the launch.
+// partials ([j][c], ld nrhs) are summed over items by k_reduce_w after the
+// launch; on this path T_b is stored [j][c] as well.
 template <int F, typename CT, typename XT, int NT>
 __device__ void contract_item_w(const KParams& kp, const CItem& it, const BlockDesc& bd,
                                 const XT* __restrict__ X, int64_t ldx, int nrhs, int c0, CT* red) {
@@ -840,7 +840,7 @@ __device__ void contract_item_w(const KParams& kp, const CItem& it, const BlockD
                 CT s = CT(0);
 #pragma unroll
                 for (int w = 0; w < kWaves; ++w) s += red[(w * NT) * 256 + idx];
-                if (j < p && c < nrhs) part[int64_t(c) * p + j] = double(s);
+                if (j < p && c < nrhs) part[int64_t(j) * nrhs + c] = double(s);
             }
             __syncthreads();
         }
@@ -865,11 +865,12 @@ __global__ __launch_bounds__(kThreads) void k_contract_w(KParams kp, const XT* _
 }
 
 // T_b = tscale .* (sum of the block's item partials, in item order): one
-// thread per output (j, c) of block blockIdx.x, 256 outputs per workgroup
-// along blockIdx.y.  fp64 blocks add in fp64, others in the accumulation type.
+// thread per output o = j * nrhs + c of block blockIdx.x, 256 outputs per
+// workgroup along blockIdx.y.  fp64 blocks add in fp64, others in the
+// accumulation type.
 template <typename CT>
-__device__ void reduce_block(const KParams& kp, const BlockDesc& bd, int o, int total) {
-    const double* src = kp.partial + kp.citems[bd.item0].poff * (total / bd.rank) + o;
+__device__ void reduce_block(const KParams& kp, const BlockDesc& bd, int o, int total, int nrhs) {
+    const double* src = kp.partial + kp.citems[bd.item0].poff * nrhs + o;
     CT s = CT(0);
     int c = 0;
     for (; c + 8 <= bd.nitems; c += 8) {
@@ -880,7 +881,7 @@ __device__ void reduce_block(const KParams& kp, const BlockDesc& bd, int o, int 
         for (int q = 0; q < 8; ++q) s += CT(v[q]);
     }
     for (; c < bd.nitems; ++c) s += CT(src[int64_t(c) * total]);
-    kp.T[bd.t_off * (total / bd.rank) + o] = double(s) * kp.tscale[bd.ts_off + o % bd.rank];
+    kp.T[bd.t_off * nrhs + o] = double(s) * kp.tscale[bd.ts_off + o / nrhs];
 }
 
 template <typename AT>
@@ -890,13 +891,14 @@ __global__ __launch_bounds__(256) void k_reduce_w(KParams kp, int nrhs) {
     const int o = blockIdx.y * 256 + threadIdx.x;
     if (o >= total) return;
     if (bd.fmt == F64)
-        reduce_block<double>(kp, bd, o, total);
+        reduce_block<double>(kp, bd, o, total, nrhs);
     else
-        reduce_block<AT>(kp, bd, o, total);
+        reduce_block<AT>(kp, bd, o, total, nrhs);
 }
 
-// rows [j0, j0 + rows) of T_b for right-hand sides [c0, c0 + CW), zero
-// beyond the rank or nrhs, as ts[j][c]
+// rows [j0, j0 + rows) of T_b (stored [j][c], ld nrhs) for right-hand
+// sides [c0, c0 + CW), zero beyond the rank or nrhs, as ts[j][c] with row
+// stride CW + 4 (the pad keeps the four lane groups' rows in different banks)
 template <typename CT, int CW>
 __device__ __forceinline__ void stage_t(const KParams& kp, const BlockDesc& bd, int j0, int rows, int c0, int nrhs,
                                         CT* ts) {
@@ -905,118 +907,181 @@ __device__ __forceinline__ void stage_t(const KParams& kp, const BlockDesc& bd, 
     for (int idx = threadIdx.x; idx < rows * CW; idx += kThreads) {
         const int jr = idx / CW, cl = idx - jr * CW;
         const int j = j0 + jr, c = c0 + cl;
-        ts[idx] = (j < p && c < nrhs) ? CT(Tb[int64_t(c) * p + j]) : CT(0);
+        ts[jr * (CW + 4) + cl] = (j < p && c < nrhs) ? CT(Tb[int64_t(j) * nrhs + c]) : CT(0);
     }
 }
 
+__device__ __forceinline__ int round4(int v) { return (v + 3) & ~3; }
+
 // One level's U_b T_b added to a wave's two 16-row tiles (accumulators in
-// the fp64 row layout).  T_b comes from LDS as ts[j][c]: either staged
-// whole before the call (`staged`, round_up(p, 32) rows), or here, kJC rows
-// at a time; rows j >= p are zero.
+// the fp64 row layout).  T_b comes from LDS as ts[j][c]: staged whole
+// before the call (jc == 0; round_up(p, 4) rows), or here, jc rows at a
+// time.  MFMA q of a 32-rank group takes ranks j0 + 4q + (l/16), so groups
+// past the rank are skipped.
 template <int F, typename CT, int NT>
 __device__ void expand_level_w(const KParams& kp, const BlockDesc& bd, int chunk0, int ld, int c0, int nrhs,
-                               bool act0, bool act1, CT* ts, bool staged, typename Mfma<CT>::acc_t acc[2][NT]) {
+                               bool act0, bool act1, CT* ts, int jc, typename Mfma<CT>::acc_t acc[2][NT]) {
     using M = Mfma<CT>;
     constexpr int S = Codec<F>::kBytes;
     constexpr int CW = 16 * NT;
+    constexpr int TS = CW + 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, g = lane >> 4;
     const int p = bd.rank;
     const uint8_t* Up = kp.fac + bd.u_off + int64_t(chunk0) * p * S;
     // fp32 results are steered into the fp64 row layout of the accumulators
     const int r0 = 32 * wave + (sizeof(CT) == 8 ? li : f64_layout_row(li)), r1 = r0 + 16;
-    for (int j0 = 0; j0 < p; j0 += kJC) {
-        const CT* tj = ts + (staged ? j0 * CW : 0);
-        if (!staged) {
+    const int stride = jc ? jc : 4 * kKL;
+    for (int j0 = 0; j0 < p; j0 += stride) {
+        const int left = p - j0 < stride ? p - j0 : stride;
+        const CT* tj = ts + (jc ? 0 : j0 * TS);
+        if (jc) {
             __syncthreads();                            // previous users of ts are done
-            stage_t<CT, CW>(kp, bd, j0, kJC, c0, nrhs, ts);
+            stage_t<CT, CW>(kp, bd, j0, round4(left), c0, nrhs, ts);
             __syncthreads();
         }
+        const int qn = (left + 3) >> 2;                 // MFMA groups holding some rank < p
         CT a0[kKL], a1[kKL];
 #pragma unroll
         for (int q = 0; q < kKL; ++q) {
-            const int j = j0 + g * kKL + q;
+            const int j = j0 + 4 * q + g;
             a0[q] = CT(0);
             a1[q] = CT(0);
-            if (j < p) {
+            if (q < qn && j < p) {
                 const uint8_t* col = Up + int64_t(j) * ld * S;
                 if (act0) Codec<F>::template load<1, CT>(col + int64_t(r0) * S, &a0[q]);
                 if (act1) Codec<F>::template load<1, CT>(col + int64_t(r1) * S, &a1[q]);
             }
         }
 #pragma unroll
-        for (int q = 0; q < kKL; ++q)
+        for (int q = 0; q < kKL; ++q) {
+            if (q >= qn) break;
 #pragma unroll
             for (int ct = 0; ct < NT; ++ct) {
-                const CT bv = tj[(g * kKL + q) * CW + 16 * ct + li];
+                const CT bv = tj[(4 * q + g) * TS + 16 * ct + li];
                 acc[0][ct] = M::mma(a0[q], bv, acc[0][ct]);
                 acc[1][ct] = M::mma(a1[q], bv, acc[1][ct]);
             }
+        }
     }
 }
 
 template <typename CT, int NT>
 __device__ void expand_level_dispatch(const KParams& kp, const BlockDesc& bd, int chunk0, int ld, int c0, int nrhs,
-                                      bool act0, bool act1, CT* ts, bool staged,
-                                      typename Mfma<CT>::acc_t acc[2][NT]) {
+                                      bool act0, bool act1, CT* ts, int jc, typename Mfma<CT>::acc_t acc[2][NT]) {
     switch (bd.fmt) {
-        case F64: expand_level_w<F64, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, staged, acc); break;
-        case F32: expand_level_w<F32, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, staged, acc); break;
-        case BF16: expand_level_w<BF16, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, staged, acc); break;
-        case F16: expand_level_w<F16, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, staged, acc); break;
-        case E4M3: expand_level_w<E4M3, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, staged, acc); break;
-        default: expand_level_w<E5M2, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, staged, acc); break;
+        case F64: expand_level_w<F64, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, jc, acc); break;
+        case F32: expand_level_w<F32, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, jc, acc); break;
+        case BF16: expand_level_w<BF16, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, jc, acc); break;
+        case F16: expand_level_w<F16, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, jc, acc); break;
+        case E4M3: expand_level_w<E4M3, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, jc, acc); break;
+        default: expand_level_w<E5M2, CT, NT>(kp, bd, chunk0, ld, c0, nrhs, act0, act1, ts, jc, acc); break;
     }
 }
 
-// a 32-row step of the leaf GEMM: the lane's D values (two 16-row tiles)
-// and its kKL rows of X for each column tile
+// Leaf GEMM operands.  X moves through LDS one 32-row step at a time
+// (double-buffered, shared by the four waves): xs[c][k], row stride kXLD.
+// The lane's D values for a step (its two 16-row tiles, its kKL columns)
+// come straight from HBM into registers, one step ahead.
+constexpr int kXLD = kStep + 4;
+
 template <typename XT, int NT>
-struct LeafStep {
+__device__ __forceinline__ int xs_bytes() { return 2 * 16 * NT * kXLD * int(sizeof(XT)); }
+
+template <typename XT, int NT>
+struct XStage {                                     // this thread's share of one X step
+    static constexpr int CW = 16 * NT;
+    static constexpr int N = (CW * (kStep / 4) + kThreads - 1) / kThreads;   // 4-element pieces
+    XT v[N][4];
+    __device__ __forceinline__ void load(const XT* Xl, int64_t ldw, int k0, int mp, int c0, int nrhs) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int e = threadIdx.x + kThreads * i;
+            const int col = e >> 3, part = e & 7;    // 8 pieces of 4 rows per column
+            const int k = k0 + 4 * part, c = c0 + col;
+            if (col < CW && k < mp && c < nrhs) {
+                const XT* src = Xl + k + ldw * c;
+                if constexpr (sizeof(XT) == 4) {
+                    const float4 a = *reinterpret_cast<const float4*>(src);
+                    v[i][0] = a.x; v[i][1] = a.y; v[i][2] = a.z; v[i][3] = a.w;
+                } else {
+                    const double2 a = reinterpret_cast<const double2*>(src)[0];
+                    const double2 b = reinterpret_cast<const double2*>(src)[1];
+                    v[i][0] = a.x; v[i][1] = a.y; v[i][2] = b.x; v[i][3] = b.y;
+                }
+            } else {
+                v[i][0] = v[i][1] = v[i][2] = v[i][3] = XT(0);
+            }
+        }
+    }
+    __device__ __forceinline__ void store(XT* xs) const {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int e = threadIdx.x + kThreads * i;
+            const int col = e >> 3, part = e & 7;
+            if (col < CW) {
+                XT* dst = xs + col * kXLD + 4 * part;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) dst[r] = v[i][r];
+            }
+        }
+    }
+};
+
+struct LeafD {                                      // the lane's D values of one step
     double a0[kKL], a1[kKL];
-    XT b[NT][kKL];
-    __device__ __forceinline__ void load(const double* Dp, int nr, const XT* Xl, int64_t ldw, int k, bool ok,
-                                         bool act0, bool act1, int r0, int r1, int c0, int li, int nrhs) {
+    __device__ __forceinline__ void load(const double* Dp, int nr, int k, bool ok, bool act0, bool act1, int r0,
+                                         int r1) {
 #pragma unroll
         for (int q = 0; q < kKL; ++q) {
             a0[q] = (ok && act0) ? Dp[int64_t(k + q) * nr + r0] : 0.0;
             a1[q] = (ok && act1) ? Dp[int64_t(k + q) * nr + r1] : 0.0;
         }
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
-            const int c = c0 + 16 * ct + li;
-            if (ok && c < nrhs)
-                load_x8<XT, XT>(Xl + k + ldw * c, b[ct]);
-            else
-#pragma unroll
-                for (int q = 0; q < kKL; ++q) b[ct][q] = XT(0);
-        }
     }
-    __device__ __forceinline__ void mma(typename Mfma<double>::acc_t acc[2][NT]) const {
+};
+
+// one step of the leaf GEMM: B operands from the LDS X step, two column
+// tiles at a time (four independent accumulators between dependent MFMAs)
+template <typename XT, int NT>
+__device__ __forceinline__ void leaf_mma(const XT* xs, const LeafD& d, int g, int li,
+                                         typename Mfma<double>::acc_t acc[2][NT]) {
+    constexpr int CP = NT >= 2 ? 2 : 1;
+#pragma unroll
+    for (int cp = 0; cp < NT; cp += CP) {
+        double b[CP][kKL];
+#pragma unroll
+        for (int u = 0; u < CP; ++u) {
+            const XT* src = xs + (16 * (cp + u) + li) * kXLD + kKL * g;
+#pragma unroll
+            for (int q = 0; q < kKL; ++q) b[u][q] = double(src[q]);
+        }
 #pragma unroll
         for (int q = 0; q < kKL; ++q)
 #pragma unroll
-            for (int ct = 0; ct < NT; ++ct) {
-                acc[0][ct] = Mfma<double>::mma(a0[q], double(b[ct][q]), acc[0][ct]);
-                acc[1][ct] = Mfma<double>::mma(a1[q], double(b[ct][q]), acc[1][ct]);
+            for (int u = 0; u < CP; ++u) {
+                acc[0][cp + u] = Mfma<double>::mma(d.a0[q], b[u][q], acc[0][cp + u]);
+                acc[1][cp + u] = Mfma<double>::mma(d.a1[q], b[u][q], acc[1][cp + u]);
             }
     }
-};
+}
 
 // Expansion tile on the matrix cores: rows [r0, r0+nr) of leaf i (at most
 // 128, a multiple of 16) for right-hand sides [c0, c0 + 16 NT).  Wave w
 // owns tile rows 32w..32w+31 as two 16-row MFMA tiles.  The fp64 leaf GEMM
 // and every fp64 level accumulate in fp64; levels decoded to fp32 (when AT
-// is float) accumulate in fp32; the sum is rounded once into Y.  When the
-// T of all the leaf's levels fits in the LDS given (lds_bytes), it is
-// staged once, before the leaf GEMM, and the levels need no barrier.
+// is float) accumulate in fp32; the sum is rounded once into Y.  LDS: the
+// two X steps, then T.  When the T of all the leaf's levels fits in the
+// rest of lds_bytes it is staged once, before the leaf GEMM, and the levels
+// need no barrier; otherwise it goes through jc-row chunks.
 template <typename XT, typename AT, int NT>
 __global__ __launch_bounds__(kThreads) void k_expand_w(KParams kp, const XT* __restrict__ Xw, int64_t ldw,
-                                                       XT* __restrict__ Y, int64_t ldy, int nrhs, int lds_bytes) {
+                                                       XT* __restrict__ Y, int64_t ldy, int nrhs, int lds_bytes,
+                                                       int jc) {
     extern __shared__ double smem_d[];
     __shared__ int s_off[kMaxDepth + 2];
     using MD = Mfma<double>;
     constexpr int CW = 16 * NT;
+    constexpr int TS = CW + 4;
     const ETile t = kp.etiles[blockIdx.x];
     const LeafDesc L = kp.leaves[t.leaf];
     const int c0 = blockIdx.y * CW;
@@ -1025,12 +1090,17 @@ __global__ __launch_bounds__(kThreads) void k_expand_w(KParams kp, const XT* __r
     const int r0 = 32 * wave + li, r1 = r0 + 16;        // tile rows of the lane's A operands
     const bool act0 = 32 * wave < t.nr, act1 = 32 * wave + 16 < t.nr;   // nr is a multiple of 16
     const int depth = kp.depth;
-    // byte offsets of each level's staged T in LDS (level k at s_off[k-1])
+    unsigned char* lds = reinterpret_cast<unsigned char*>(smem_d);
+    XT* xs0 = reinterpret_cast<XT*>(lds);
+    XT* xs1 = xs0 + CW * kXLD;
+    unsigned char* tl = lds + xs_bytes<XT, NT>();
+    const int t_bytes = lds_bytes - xs_bytes<XT, NT>();
+    // byte offsets of each level's staged T (level k at s_off[k-1])
     if (threadIdx.x < depth) {
         const int k = threadIdx.x + 1;
         const BlockDesc& bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
         const int w = (sizeof(AT) == 8 || bd.fmt == F64) ? 8 : 4;
-        s_off[k] = ((bd.rank + kJC - 1) / kJC) * kJC * CW * w;
+        s_off[k] = round4(bd.rank) * TS * w;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1043,16 +1113,14 @@ __global__ __launch_bounds__(kThreads) void k_expand_w(KParams kp, const XT* __r
         s_off[depth] = off;
     }
     __syncthreads();
-    const bool staged = s_off[depth] <= lds_bytes;
-    unsigned char* lds = reinterpret_cast<unsigned char*>(smem_d);
+    const bool staged = s_off[depth] <= t_bytes;
     if (staged) {
         for (int k = 1; k <= depth; ++k) {
             const BlockDesc& bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
-            const int rows = ((bd.rank + kJC - 1) / kJC) * kJC;
             if (sizeof(AT) == 8 || bd.fmt == F64)
-                stage_t<double, CW>(kp, bd, 0, rows, c0, nrhs, reinterpret_cast<double*>(lds + s_off[k - 1]));
+                stage_t<double, CW>(kp, bd, 0, round4(bd.rank), c0, nrhs, reinterpret_cast<double*>(tl + s_off[k - 1]));
             else
-                stage_t<float, CW>(kp, bd, 0, rows, c0, nrhs, reinterpret_cast<float*>(lds + s_off[k - 1]));
+                stage_t<float, CW>(kp, bd, 0, round4(bd.rank), c0, nrhs, reinterpret_cast<float*>(tl + s_off[k - 1]));
         }
     }
     MD::acc_t accd[2][NT];
@@ -1060,54 +1128,59 @@ __global__ __launch_bounds__(kThreads) void k_expand_w(KParams kp, const XT* __r
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < NT; ++b) zero_acc(accd[a][b]);
-    // leaf: D_i (tile rows, all mp columns; column-major, ld = nr) times X_i,
-    // two steps in flight
+    // leaf: D_i (tile rows, all mp columns; column-major, ld = nr) times X_i
     {
         const double* Dp = kp.leafd + L.d_off + int64_t(t.r0) * L.mp;
         const XT* Xl = Xw + L.prow0;
-        if constexpr (NT >= 8) {                        // 128 columns: one step at a time (registers)
-            LeafStep<XT, NT> sa;
-            for (int k0 = 0; k0 < L.mp; k0 += kStep) {
-                const int k = k0 + g * kKL;
-                sa.load(Dp, t.nr, Xl, ldw, k, k < L.mp, act0, act1, r0, r1, c0, li, nrhs);
-                sa.mma(accd);
+        const int nstep = (L.mp + kStep - 1) / kStep;
+        XStage<XT, NT> xr;
+        LeafD da, db;
+        xr.load(Xl, ldw, 0, L.mp, c0, nrhs);
+        da.load(Dp, t.nr, kKL * g, kKL * g < L.mp, act0, act1, r0, r1);   // mp and k are multiples of 8
+        xr.store(xs0);
+        __syncthreads();
+        for (int s = 0; s < nstep; s += 2) {
+            const int k1 = (s + 1) * kStep, k2 = (s + 2) * kStep;
+            if (s + 1 < nstep) {
+                xr.load(Xl, ldw, k1, L.mp, c0, nrhs);
+                db.load(Dp, t.nr, k1 + kKL * g, k1 + kKL * g < L.mp, act0, act1, r0, r1);
             }
-        } else {
-            LeafStep<XT, NT> sa, sb;
-            sa.load(Dp, t.nr, Xl, ldw, g * kKL, g * kKL < L.mp, act0, act1, r0, r1, c0, li, nrhs);
-            for (int k0 = 0; k0 < L.mp; k0 += 2 * kStep) {
-                const int kb = k0 + kStep + g * kKL;     // mp and k are multiples of 8
-                sb.load(Dp, t.nr, Xl, ldw, kb, kb < L.mp, act0, act1, r0, r1, c0, li, nrhs);
-                sa.mma(accd);
-                if (k0 + kStep >= L.mp) break;
-                const int ka = k0 + 2 * kStep + g * kKL;
-                sa.load(Dp, t.nr, Xl, ldw, ka, ka < L.mp, act0, act1, r0, r1, c0, li, nrhs);
-                sb.mma(accd);
+            leaf_mma<XT, NT>(xs0, da, g, li, accd);
+            if (s + 1 < nstep) xr.store(xs1);
+            __syncthreads();
+            if (s + 1 >= nstep) break;
+            if (s + 2 < nstep) {
+                xr.load(Xl, ldw, k2, L.mp, c0, nrhs);
+                da.load(Dp, t.nr, k2 + kKL * g, k2 + kKL * g < L.mp, act0, act1, r0, r1);
             }
+            leaf_mma<XT, NT>(xs1, db, g, li, accd);
+            if (s + 2 < nstep) xr.store(xs0);
+            __syncthreads();
         }
     }
-    if (staged) __syncthreads();                        // T of every level is in LDS
-    // the depth ancestors' blocks whose rows contain this leaf
+    // the depth ancestors' blocks whose rows contain this leaf (T staged
+    // before the leaf GEMM is visible: its loop ended with a barrier)
     typename Mfma<AT>::acc_t accl[2][NT];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < NT; ++b) zero_acc(accl[a][b]);
+    const int jcu = staged ? 0 : jc;
     for (int k = 1; k <= depth; ++k) {
         const BlockDesc bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
         if (bd.rank == 0) continue;
         const int chunk0 = L.prow0 - bd.urow0 + t.r0;   // the tile's chunk of the U panel
-        unsigned char* ts = lds + (staged ? s_off[k - 1] : 0);
+        unsigned char* ts = tl + (staged ? s_off[k - 1] : 0);
         if constexpr (sizeof(AT) == 8) {
             expand_level_dispatch<double, NT>(kp, bd, chunk0, t.nr, c0, nrhs, act0, act1,
-                                              reinterpret_cast<double*>(ts), staged, accd);
+                                              reinterpret_cast<double*>(ts), jcu, accd);
         } else {
             if (bd.fmt == F64)
                 expand_level_dispatch<double, NT>(kp, bd, chunk0, t.nr, c0, nrhs, act0, act1,
-                                                  reinterpret_cast<double*>(ts), staged, accd);
+                                                  reinterpret_cast<double*>(ts), jcu, accd);
             else
                 expand_level_dispatch<float, NT>(kp, bd, chunk0, t.nr, c0, nrhs, act0, act1,
-                                                 reinterpret_cast<float*>(ts), staged, accl);
+                                                 reinterpret_cast<float*>(ts), jcu, accl);
         }
     }
     // Y rows g+4e of each 16-row tile (fp64 layout), column li of each column tile
@@ -1145,13 +1218,21 @@ hipError_t launch_wide_nt(const KParams& kp, const XT* Xw, int64_t ldw, XT* Y, i
         hipLaunchKernelGGL((k_reduce_w<AT>), dim3(kp.nblocks, unsigned(rows_y)), dim3(256), 0, s, kp, nrhs);
         tm.end(3);
     }
-    // LDS: T of all levels when it fits in 64 KB, else kJC rows at a time
-    const int64_t all = int64_t(kp.max_tstage) * CW;
-    const int64_t chunk = int64_t(kJC) * CW * 8;
-    const int64_t lds = all <= kMaxLds ? (all > chunk ? all : chunk) : chunk;
+    // LDS: two X steps, then T of all levels if it fits in 64 KB, else T
+    // in chunks of 32 (or 16) rows
+    const int64_t xb = 2 * int64_t(CW) * kXLD * sizeof(XT);
+    const int64_t all = int64_t(kp.max_tstage) * (CW + 4);
+    const int64_t ch32 = int64_t(32) * (CW + 4) * 8, ch16 = ch32 / 2;
+    int jc = 0;
+    int64_t lds = xb + all;
+    if (lds > kMaxLds) {
+        jc = xb + ch32 <= kMaxLds ? 32 : 16;
+        lds = xb + (jc == 32 ? ch32 : ch16);
+        if (lds > kMaxLds) return hipErrorInvalidConfiguration;
+    }
     tm.begin(2);
     hipLaunchKernelGGL((k_expand_w<XT, AT, NT>), dim3(kp.netiles, (nrhs + CW - 1) / CW), dim3(kThreads),
-                       size_t(lds), s, kp, Xw, ldw, Y, ldy, nrhs, int(lds));
+                       size_t(lds), s, kp, Xw, ldw, Y, ldy, nrhs, int(lds), jc);
     tm.end(2);
     return hipGetLastError();
 }
@@ -1174,7 +1255,7 @@ hipError_t launch_wide(const KParams& kp, const void* Xv, int64_t ldx, void* Yv,
     }
     if (nrhs <= 16) return launch_wide_nt<XT, AT, 1>(kp, Xw, ldw, Y, ldy, nrhs, tm);
     if (nrhs <= 32) return launch_wide_nt<XT, AT, 2>(kp, Xw, ldw, Y, ldy, nrhs, tm);
-    if (nrhs <= 64) return launch_wide_nt<XT, AT, 4>(kp, Xw, ldw, Y, ldy, nrhs, tm);
+    if (nrhs <= 64 || sizeof(XT) == 8) return launch_wide_nt<XT, AT, 4>(kp, Xw, ldw, Y, ldy, nrhs, tm);
     return launch_wide_nt<XT, AT, 8>(kp, Xw, ldw, Y, ldy, nrhs, tm);
 }
 
