@@ -188,9 +188,28 @@ hodlr_status hodlr_export_block(hodlr_op op, int32_t block, void* u_codes, int8_
 hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int64_t ldy,
                           int32_t nrhs, int32_t xy_dtype, void* stream);
 
-/* count independent products Y_i = A_i X_i in one persistent launch.
- * Operators may differ in everything but must live on the same device.
- * Arrays of length count. */
+/* count independent products Y_i = A_i X_i (each as hodlr_matvec defines
+ * it; the paper treats one operator at a time, this is the batch of many).
+ * Operators may differ in size, depth, ranks, formats, nrhs and dtype but
+ * must live on one device; arrays have length count; each Y_i is
+ * overwritten.  A handle may appear only once per batch (its workspace
+ * serves one product at a time; E_ARG otherwise).  Operators that share a kernel variant (X/Y dtype,
+ * accumulation, wave or matrix-core path, right-hand-side grouping) run
+ * together: one persistent launch per phase walks a work list of all their
+ * units (leaves, contraction items, T reductions, expansion tiles), so the
+ * whole batch is a handful of launches.
+ * The first call with a given signature (handles and their current images,
+ * X/Y pointers, leading dimensions, nrhs, dtypes, stream) builds a plan:
+ * it uploads the work lists (device memory held until a handle in it is
+ * destroyed or 32 newer plans evict it), times the candidate launch shapes
+ * on `stream` (work order longest-first or as given; 1, 2, 4 or 8
+ * workgroups per compute unit; skipped when the environment sets
+ * HODLR_BATCH_TUNE=0), keeps the fastest and captures the launches into a
+ * HIP graph.  Later calls with the same signature replay that graph.  On a
+ * stream that is being captured the launches are recorded into the
+ * caller's graph instead; that needs a plan made by an earlier call outside
+ * capture (E_STATE otherwise), since nothing may be allocated during a
+ * capture.  Argument errors are reported before anything is enqueued. */
 hodlr_status hodlr_matvec_batched(const hodlr_op* ops, int32_t count, const void* const* X,
                                   const int64_t* ldx, void* const* Y, const int64_t* ldy,
                                   const int32_t* nrhs, const int32_t* xy_dtype, void* stream);

@@ -142,4 +142,59 @@ int launch_matvec(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_
                   int nrhs, bool xy_double, bool acc_double, void* stream, void* const* events,
                   bool* ran);
 
+// ---------------------------------------------------------------------------
+// batched products: persistent launches over many operators
+// ---------------------------------------------------------------------------
+// How one product of one operator is launched (chosen as the
+// single-operator path chooses it).
+struct OpLaunch {
+    int32_t wide;              // matrix-core path (nrhs >= 16)
+    int32_t rg;                // wave path: right-hand sides per pass; matrix-core path: 16-column tiles
+    int32_t ntc;               // matrix-core contraction: 16-column tiles
+    int32_t padx;              // X goes through the padded copy
+    int32_t stage_cap;         // wave contraction: LDS doubles for the last arriver's staging
+    int32_t jc;                // matrix-core expansion: T chunk rows when not staged whole
+    int64_t lds_contract;
+    int64_t lds_expand;
+    int32_t gy_contract;       // matrix-core: right-hand-side groups of the contraction
+    int32_t gy_expand;         // ... and of the expansion
+};
+
+struct BatchOp {               // one operator of a batched product (device array)
+    KParams kp;
+    const void* X;             // caller's X (ld ldx)
+    const void* Xc;            // X as the contraction (and the matrix-core expansion) reads it
+    void* Y;
+    int64_t ldx, ldc, ldy;
+    int32_t nrhs;
+    int32_t pad_;
+};
+
+struct WorkItem {              // (operator, leaf / item / block / tile, right-hand-side group)
+    int32_t op;
+    int32_t idx;
+    int32_t y;
+    int32_t pad_;
+};
+
+// One persistent launch per phase for the operators sharing a kernel variant.
+struct BatchGroup {
+    int32_t xy_double, acc_double, wide, rg, ntc;
+    int32_t stage_cap, jc;
+    int64_t lds_contract, lds_expand;
+    const BatchOp* ops;        // device
+    const WorkItem* padx;      // device arrays and their lengths
+    const WorkItem* contract;
+    const WorkItem* reduce;
+    const WorkItem* expand;
+    int32_t n_padx, n_contract, n_reduce, n_expand;
+    int32_t grid[4];           // workgroups of the four persistent launches
+};
+
+// 0 on success, else a hipError_t value (hipErrorInvalidConfiguration: LDS
+// needs beyond 64 KB).
+int plan_launch(const KParams& kp, const void* X, int64_t ldx, int nrhs, bool xy_double, bool acc_double,
+                OpLaunch* out);
+int launch_batch_group(const BatchGroup& g, void* stream);
+
 }  // namespace hodlr

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -223,9 +224,12 @@ struct Workspace {
     void* xpad = nullptr;
     int32_t* sync = nullptr;   // counters of the fused launch; zeroed once, self-resetting
     int64_t cap_partial = 0, cap_T = 0, cap_xpad = 0, cap_sync = 0;
+    uint64_t gen = 0;          // bumped whenever a buffer is replaced (batched plans keep pointers)
 };
 
 struct hodlr_op_s {
+    uint64_t uid = 0;          // unique per handle in this process
+    uint64_t gen = 0;          // bumped by every pack (device image replaced)
     int64_t n = 0;
     int depth = 0;
     int nb = 0;
@@ -451,6 +455,7 @@ void node_rowlocs(const hodlr_op_s* op, int k, int64_t j, int64_t chunk_rows, st
 // (for device handles) upload it.  Called after create and after every
 // precision change.
 hodlr_status pack(hodlr_op_s* op) {
+    ++op->gen;
     const int nb = op->nb;
     op->bdesc.assign(nb, BlockDesc{});
     op->citems.clear();
@@ -716,6 +721,8 @@ hodlr_status hodlr_create(hodlr_op* out, int64_t n, int32_t depth, const int64_t
     if (device < -1) return fail(HODLR_E_ARG, "device must be >= -1");
     std::unique_ptr<hodlr_op_s> op(new (std::nothrow) hodlr_op_s);
     if (!op) return fail(HODLR_E_NOMEM, "operator");
+    static std::atomic<uint64_t> next_uid{1};
+    op->uid = next_uid++;
     op->n = n;
     op->depth = depth;
     op->nleaves = 1 << depth;
@@ -994,7 +1001,8 @@ hodlr_status hodlr_export_block(hodlr_op op, int32_t block, void* u_codes, int8_
 
 namespace {
 
-hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_double, KParams* kp) {
+hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_double, KParams* kp,
+                               uint64_t* ws_gen = nullptr) {
     std::lock_guard<std::mutex> lk(op->ws_mu);
     Workspace& w = op->ws[stream];
     const int64_t need_p = std::max<int64_t>(1, op->total_item_rank * nrhs);
@@ -1018,6 +1026,7 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
             return fail(HODLR_E_NOMEM, "workspace %s (%lld bytes)", what, (long long)bytes);
         }
         *cap = bytes;
+        ++w.gen;
         return HODLR_OK;
     };
     hodlr_status r;
@@ -1055,7 +1064,338 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
     kp->ncitems = int32_t(op->citems.size());
     kp->netiles = int32_t(op->etiles.size());
     kp->padded = op->padded ? 1 : 0;
+    if (ws_gen) *ws_gen = w.gen;
     return HODLR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched products: plan, autotune, capture, replay
+// ---------------------------------------------------------------------------
+// A plan holds, for one batch signature (operators with their image and
+// workspace generations, X/Y pointers and leading dimensions, nrhs, dtypes,
+// stream), the device copies of the per-operator launch records and of the
+// work lists of every kernel-variant group, the launch shape chosen by the
+// autotuner, and a HIP graph of the launches.  The autotuner times every
+// candidate (work order: longest first or natural; persistent grid: 1, 2,
+// 4 or 8 workgroups per compute unit) on the caller's stream the first time
+// a signature is seen, unless the stream is capturing or HODLR_BATCH_TUNE=0.
+struct BatchPlan {
+    std::vector<uint64_t> uids;
+    void* d_buf = nullptr;
+    std::vector<BatchGroup> groups[2];   // [order]: 0 longest first, 1 natural
+    int order = 0, mult = 2;
+    float tuned_ms = 0.0f;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+    ~BatchPlan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (d_buf) (void)hipFree(d_buf);
+    }
+};
+
+std::mutex g_batch_mu;
+std::map<std::vector<uint64_t>, std::unique_ptr<BatchPlan>> g_plans;
+uint64_t g_batch_clock = 0;
+constexpr size_t kMaxPlans = 32;
+
+void batch_forget(uint64_t uid) {      // plans that name a destroyed operator
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (auto it = g_plans.begin(); it != g_plans.end();) {
+        if (std::find(it->second->uids.begin(), it->second->uids.end(), uid) != it->second->uids.end())
+            it = g_plans.erase(it);
+        else
+            ++it;
+    }
+}
+
+int compute_units(int device) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
+        cus = 256;
+    return cus;
+}
+
+void set_grids(std::vector<BatchGroup>& gs, int cus, int mult) {
+    for (auto& g : gs) {
+        const int32_t n[4] = {g.n_padx, g.n_contract, g.n_reduce, g.n_expand};
+        for (int ph = 0; ph < 4; ++ph) g.grid[ph] = std::max(1, std::min(n[ph], cus * mult));
+    }
+}
+
+hipError_t launch_groups(const std::vector<BatchGroup>& gs, hipStream_t s) {
+    // phase by phase across groups (each group's own launches stay in order)
+    for (const auto& g : gs) {
+        const int r = launch_batch_group(g, s);
+        if (r) return hipError_t(r);
+    }
+    return hipSuccess;
+}
+
+struct GroupBuild {
+    BatchGroup g{};
+    std::vector<BatchOp> ops;
+    std::vector<std::pair<int64_t, WorkItem>> work[4];   // (cost, item) per phase
+};
+
+hodlr_status build_plan(const hodlr_op* ops, int count, const void* const* X, const int64_t* ldx,
+                        void* const* Y, const int64_t* ldy, const int32_t* nrhs, const int32_t* xy_dtype,
+                        void* stream, BatchPlan* plan) {
+    std::map<std::vector<int32_t>, GroupBuild> groups;
+    for (int i = 0; i < count; ++i) {
+        hodlr_op op = ops[i];
+        const bool xyd = xy_dtype[i] == HODLR_FP64;
+        KParams kp{};
+        hodlr_status r = prepare_workspace(op, stream, nrhs[i], xyd, &kp);
+        if (r != HODLR_OK) return r;
+        OpLaunch ol{};
+        if (plan_launch(kp, X[i], ldx[i], nrhs[i], xyd, op->acc_double, &ol) != 0)
+            return fail(HODLR_E_UNSUPPORTED, "operator %d: leaf size %d with path rank %d needs more than 64 KB of LDS",
+                        i, op->max_leaf, op->max_rank_path);
+        const std::vector<int32_t> key = {xyd ? 1 : 0, op->acc_double ? 1 : 0, ol.wide, ol.rg};
+        GroupBuild& gb = groups[key];
+        BatchGroup& g = gb.g;
+        if (gb.ops.empty()) {
+            g.xy_double = key[0];
+            g.acc_double = key[1];
+            g.wide = ol.wide;
+            g.rg = ol.rg;
+            g.ntc = ol.ntc;
+            g.jc = 0;
+        }
+        g.stage_cap = std::max(g.stage_cap, ol.stage_cap);
+        g.lds_contract = std::max(g.lds_contract, ol.lds_contract);
+        g.lds_expand = std::max(g.lds_expand, ol.lds_expand);
+        if (ol.jc) g.jc = g.jc ? std::min(g.jc, ol.jc) : ol.jc;
+        const int32_t oi = int32_t(gb.ops.size());
+        BatchOp bo{};
+        bo.kp = kp;
+        bo.X = X[i];
+        bo.ldx = ldx[i];
+        bo.Y = Y[i];
+        bo.ldy = ldy[i];
+        bo.nrhs = nrhs[i];
+        bo.Xc = ol.padx ? kp.xpad : X[i];
+        bo.ldc = ol.padx ? op->npad : ldx[i];
+        gb.ops.push_back(bo);
+        const int64_t s_rhs = nrhs[i];
+        if (ol.padx)
+            for (int l = 0; l < op->nleaves; ++l)
+                gb.work[0].push_back({int64_t(op->ldesc[l].mp) * s_rhs, WorkItem{oi, l, 0, 0}});
+        const int gyc = ol.wide ? ol.gy_contract : 1;
+        for (int c = 0; c < int(op->citems.size()); ++c) {
+            const CItem& it = op->citems[c];
+            const BlockDesc& bd = op->bdesc[it.block];
+            const int64_t cost = int64_t(it.nr) * bd.rank * fmt_bytes(bd.fmt) + int64_t(it.nr) * 4 * s_rhs;
+            for (int y = 0; y < gyc; ++y) gb.work[1].push_back({cost, WorkItem{oi, c, y, 0}});
+        }
+        if (ol.wide && !op->citems.empty())
+            for (int b = 0; b < op->nb; ++b) {
+                const int64_t total = int64_t(op->bdesc[b].rank) * nrhs[i];
+                for (int64_t y = 0; y * 256 < total; ++y)
+                    gb.work[2].push_back({int64_t(op->bdesc[b].nitems), WorkItem{oi, b, int32_t(y), 0}});
+            }
+        const int gye = ol.wide ? ol.gy_expand : 1;
+        for (int t = 0; t < int(op->etiles.size()); ++t) {
+            const ETile& et = op->etiles[t];
+            const LeafDesc& L = op->ldesc[et.leaf];
+            int64_t cost = int64_t(et.nr) * L.mp * 8;
+            for (int k = 1; k <= op->depth; ++k) {
+                const BlockDesc& bd = op->bdesc[((1 << k) - 2) + (et.leaf >> (op->depth - k))];
+                cost += int64_t(et.nr) * bd.rank * fmt_bytes(bd.fmt);
+            }
+            for (int y = 0; y < gye; ++y) gb.work[3].push_back({cost, WorkItem{oi, t, y, 0}});
+        }
+    }
+    // device image: per group its ops, then the work lists in both orders
+    size_t bytes = 0;
+    auto reserve = [&](size_t n) {
+        const size_t off = bytes;
+        bytes = (bytes + n + 255) / 256 * 256;
+        return off;
+    };
+    struct Offs { size_t ops, work[2][4]; };
+    std::vector<Offs> offs;
+    for (auto& kv : groups) {
+        Offs o{};
+        o.ops = reserve(kv.second.ops.size() * sizeof(BatchOp));
+        for (int ord = 0; ord < 2; ++ord)
+            for (int ph = 0; ph < 4; ++ph) o.work[ord][ph] = reserve(kv.second.work[ph].size() * sizeof(WorkItem));
+        offs.push_back(o);
+    }
+    std::vector<uint8_t> img(std::max<size_t>(bytes, 256), 0);
+    size_t gi = 0;
+    for (auto& kv : groups) {
+        GroupBuild& gb = kv.second;
+        const Offs& o = offs[gi++];
+        std::memcpy(img.data() + o.ops, gb.ops.data(), gb.ops.size() * sizeof(BatchOp));
+        for (int ph = 0; ph < 4; ++ph) {
+            auto& w = gb.work[ph];
+            std::vector<WorkItem> natural(w.size()), sorted(w.size());
+            for (size_t q = 0; q < w.size(); ++q) natural[q] = w[q].second;
+            std::stable_sort(w.begin(), w.end(), [](const std::pair<int64_t, WorkItem>& a,
+                                                    const std::pair<int64_t, WorkItem>& b) {
+                return a.first > b.first;
+            });
+            for (size_t q = 0; q < w.size(); ++q) sorted[q] = w[q].second;
+            std::memcpy(img.data() + o.work[0][ph], sorted.data(), sorted.size() * sizeof(WorkItem));
+            std::memcpy(img.data() + o.work[1][ph], natural.data(), natural.size() * sizeof(WorkItem));
+        }
+    }
+    hipError_t e = hipMalloc(&plan->d_buf, img.size());
+    if (e != hipSuccess) {
+        plan->d_buf = nullptr;
+        (void)hipGetLastError();
+        return fail(HODLR_E_NOMEM, "batch plan (%zu bytes)", img.size());
+    }
+    e = hipMemcpy(plan->d_buf, img.data(), img.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "uploading the batch plan");
+    uint8_t* base = static_cast<uint8_t*>(plan->d_buf);
+    gi = 0;
+    for (auto& kv : groups) {
+        const GroupBuild& gb = kv.second;
+        const Offs& o = offs[gi++];
+        for (int ord = 0; ord < 2; ++ord) {
+            BatchGroup g = gb.g;
+            g.ops = reinterpret_cast<const BatchOp*>(base + o.ops);
+            g.padx = reinterpret_cast<const WorkItem*>(base + o.work[ord][0]);
+            g.contract = reinterpret_cast<const WorkItem*>(base + o.work[ord][1]);
+            g.reduce = reinterpret_cast<const WorkItem*>(base + o.work[ord][2]);
+            g.expand = reinterpret_cast<const WorkItem*>(base + o.work[ord][3]);
+            g.n_padx = int32_t(gb.work[0].size());
+            g.n_contract = int32_t(gb.work[1].size());
+            g.n_reduce = int32_t(gb.work[2].size());
+            g.n_expand = int32_t(gb.work[3].size());
+            plan->groups[ord].push_back(g);
+        }
+    }
+    for (int i = 0; i < count; ++i) plan->uids.push_back(ops[i]->uid);
+    return ok();
+}
+
+hodlr_status tune_plan(BatchPlan* plan, int device, hipStream_t s) {
+    const int cus = compute_units(device);
+    const char* env = std::getenv("HODLR_BATCH_TUNE");
+    if (env && env[0] == '0') {
+        set_grids(plan->groups[plan->order], cus, plan->mult);
+        return ok();
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipGetLastError();
+        return fail(HODLR_E_DEVICE, "events for the batch autotuner");
+    }
+    float best = -1.0f;
+    const int mults[4] = {1, 2, 4, 8};
+    hodlr_status st = HODLR_OK;
+    for (int ord = 0; ord < 2 && st == HODLR_OK; ++ord)
+        for (int m : mults) {
+            set_grids(plan->groups[ord], cus, m);
+            hipError_t e = launch_groups(plan->groups[ord], s);     // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = launch_groups(plan->groups[ord], s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                st = hip_fail(e, "batch autotuner");
+                break;
+            }
+            if (best < 0.0f || ms < best) {
+                best = ms;
+                plan->order = ord;
+                plan->mult = m;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != HODLR_OK) return st;
+    plan->tuned_ms = best / 3.0f;
+    set_grids(plan->groups[plan->order], cus, plan->mult);
+    return ok();
+}
+
+hodlr_status capture_plan(BatchPlan* plan) {
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const hipError_t le = launch_groups(plan->groups[plan->order], cs);
+        e = hipStreamEndCapture(cs, &plan->graph);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(e, "capturing the batch graph");
+    return ok();
+}
+
+hodlr_status batch_run(const hodlr_op* ops, int count, const void* const* X, const int64_t* ldx, void* const* Y,
+                       const int64_t* ldy, const int32_t* nrhs, const int32_t* xy_dtype, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cap);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    const bool capturing = cap == hipStreamCaptureStatusActive;
+    // signature (after making sure every workspace is large enough)
+    std::vector<uint64_t> key;
+    key.reserve(size_t(count) * 10 + 1);
+    key.push_back(reinterpret_cast<uintptr_t>(stream));
+    for (int i = 0; i < count; ++i) {
+        KParams kp{};
+        uint64_t wg = 0;
+        if (capturing) {
+            // nothing may be allocated while capturing: use the workspace as it is
+            std::lock_guard<std::mutex> lk(ops[i]->ws_mu);
+            auto it = ops[i]->ws.find(stream);
+            if (it == ops[i]->ws.end())
+                return fail(HODLR_E_STATE, "operator %d: no workspace on this stream; run the batch once "
+                                           "outside capture first", i);
+            wg = it->second.gen;
+        } else {
+            hodlr_status r = prepare_workspace(ops[i], stream, nrhs[i], xy_dtype[i] == HODLR_FP64, &kp, &wg);
+            if (r != HODLR_OK) return r;
+        }
+        key.insert(key.end(), {ops[i]->uid, ops[i]->gen, wg, uint64_t(reinterpret_cast<uintptr_t>(X[i])),
+                               uint64_t(ldx[i]), uint64_t(reinterpret_cast<uintptr_t>(Y[i])), uint64_t(ldy[i]),
+                               uint64_t(nrhs[i]), uint64_t(xy_dtype[i])});
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    auto it = g_plans.find(key);
+    if (it == g_plans.end()) {
+        // a plan is built (allocated, uploaded, tuned, captured) outside capture only; the
+        // signature pins the workspaces it was built with, so a capture that finds it is safe
+        if (capturing)
+            return fail(HODLR_E_STATE, "batch not seen before on this stream with these arguments; run it "
+                                       "once outside capture first");
+        if (g_plans.size() >= kMaxPlans) {            // drop the least recently used plan
+            auto lru = g_plans.begin();
+            for (auto q = g_plans.begin(); q != g_plans.end(); ++q)
+                if (q->second->last_use < lru->second->last_use) lru = q;
+            (void)hipDeviceSynchronize();
+            g_plans.erase(lru);
+        }
+        std::unique_ptr<BatchPlan> plan(new (std::nothrow) BatchPlan);
+        if (!plan) return fail(HODLR_E_NOMEM, "batch plan");
+        hodlr_status r = build_plan(ops, count, X, ldx, Y, ldy, nrhs, xy_dtype, stream, plan.get());
+        if (r != HODLR_OK) return r;
+        r = tune_plan(plan.get(), ops[0]->device, s);
+        if (r == HODLR_OK) r = capture_plan(plan.get());
+        if (r != HODLR_OK) return r;
+        it = g_plans.emplace(key, std::move(plan)).first;
+    }
+    BatchPlan* plan = it->second.get();
+    plan->last_use = ++g_batch_clock;
+    if (capturing || !plan->exec)
+        e = launch_groups(plan->groups[plan->order], s);     // the caller's capture records the launches
+    else
+        e = hipGraphLaunch(plan->exec, s);
+    if (e != hipSuccess) return hip_fail(e, "batched launch");
+    return ok();
 }
 
 }  // namespace
@@ -1101,14 +1441,25 @@ hodlr_status hodlr_matvec_batched(const hodlr_op* ops, int32_t count, const void
     if (count == 0) return ok();
     if (!ops || !X || !ldx || !Y || !ldy || !nrhs || !xy_dtype) return fail(HODLR_E_ARG, "NULL array");
     for (int i = 0; i < count; ++i) {
-        if (!ops[i]) return fail(HODLR_E_ARG, "ops[%d] is NULL", i);
-        if (ops[i]->device != ops[0]->device) return fail(HODLR_E_STATE, "operators on different devices");
+        hodlr_op op = ops[i];
+        if (!op) return fail(HODLR_E_ARG, "ops[%d] is NULL", i);
+        if (op->device < 0) return fail(HODLR_E_STATE, "ops[%d] is a host-only handle", i);
+        if (op->device != ops[0]->device) return fail(HODLR_E_STATE, "operators on different devices");
+        if (nrhs[i] < 1) return fail(HODLR_E_ARG, "nrhs[%d] must be >= 1", i);
+        if (xy_dtype[i] != HODLR_FP32 && xy_dtype[i] != HODLR_FP64)
+            return fail(HODLR_E_UNSUPPORTED, "xy_dtype[%d] must be HODLR_FP32 or HODLR_FP64", i);
+        if (!X[i] || !Y[i]) return fail(HODLR_E_ARG, "X[%d] or Y[%d] is NULL", i, i);
+        if (ldx[i] < op->n || ldy[i] < op->n) return fail(HODLR_E_ARG, "ldx[%d] and ldy[%d] must be >= n", i, i);
     }
-    for (int i = 0; i < count; ++i) {
-        hodlr_status r = hodlr_matvec(ops[i], X[i], ldx[i], Y[i], ldy[i], nrhs[i], xy_dtype[i], stream);
-        if (r != HODLR_OK) return fail(r, "operator %d: %s", i, g_last_error.c_str());
+    {   // each operator's workspace serves one product at a time
+        std::vector<hodlr_op> sorted(ops, ops + count);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return fail(HODLR_E_ARG, "an operator appears more than once in the batch");
     }
-    return ok();
+    hipError_t e = hipSetDevice(ops[0]->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return batch_run(ops, count, X, ldx, Y, ldy, nrhs, xy_dtype, stream);
 }
 
 hodlr_status hodlr_profile(hodlr_op op, int32_t capacity) {
@@ -1163,6 +1514,7 @@ hodlr_status hodlr_destroy(hodlr_op op) {
         (void)hipSetDevice(op->device);
         (void)hipDeviceSynchronize();
     }
+    batch_forget(op->uid);
     free_device(op);
     delete op;
     return ok();

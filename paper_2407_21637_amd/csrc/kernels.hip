@@ -608,14 +608,19 @@ __global__ __launch_bounds__(kThreads, HODLR_EXPAND_MINW) void k_expand(KParams 
 // padded copy of X (only when some leaf size is not a multiple of 16)
 // ---------------------------------------------------------------------------
 template <typename XT>
-__global__ __launch_bounds__(256) void k_padx(KParams kp, const XT* __restrict__ X, int64_t ldx, int nrhs) {
-    const LeafDesc L = kp.leaves[blockIdx.x];
+__device__ void padx_leaf(const KParams& kp, int leaf, const XT* __restrict__ X, int64_t ldx, int nrhs) {
+    const LeafDesc L = kp.leaves[leaf];
     XT* Xp = static_cast<XT*>(kp.xpad);
     const int64_t total = int64_t(L.mp) * nrhs;
     for (int64_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
         const int64_t r = idx % L.mp, c = idx / L.mp;
         Xp[L.prow0 + r + kp.npad * c] = r < L.m ? X[L.row0 + r + ldx * c] : XT(0);
     }
+}
+
+template <typename XT>
+__global__ __launch_bounds__(256) void k_padx(KParams kp, const XT* __restrict__ X, int64_t ldx, int nrhs) {
+    padx_leaf<XT>(kp, blockIdx.x, X, ldx, nrhs);
 }
 
 struct Timer {            // optional event pair around each phase
@@ -848,12 +853,11 @@ __device__ void contract_item_w(const KParams& kp, const CItem& it, const BlockD
 }
 
 template <typename XT, typename AT, int NT>
-__global__ __launch_bounds__(kThreads) void k_contract_w(KParams kp, const XT* __restrict__ Xc, int64_t ldc,
-                                                         int nrhs) {
-    extern __shared__ double smem_d[];
-    const CItem it = kp.citems[blockIdx.x];
+__device__ void run_contract_w(const KParams& kp, int item, int yg, const XT* __restrict__ Xc, int64_t ldc,
+                               int nrhs, double* smem_d) {
+    const CItem it = kp.citems[item];
     const BlockDesc bd = kp.blocks[it.block];
-    const int c0 = blockIdx.y * 16 * NT;
+    const int c0 = yg * 16 * NT;
     switch (bd.fmt) {
         case F64: contract_item_w<F64, double, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<double*>(smem_d)); break;
         case F32: contract_item_w<F32, AT, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<AT*>(smem_d)); break;
@@ -862,6 +866,13 @@ __global__ __launch_bounds__(kThreads) void k_contract_w(KParams kp, const XT* _
         case E4M3: contract_item_w<E4M3, AT, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<AT*>(smem_d)); break;
         default: contract_item_w<E5M2, AT, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<AT*>(smem_d)); break;
     }
+}
+
+template <typename XT, typename AT, int NT>
+__global__ __launch_bounds__(kThreads) void k_contract_w(KParams kp, const XT* __restrict__ Xc, int64_t ldc,
+                                                         int nrhs) {
+    extern __shared__ double smem_d[];
+    run_contract_w<XT, AT, NT>(kp, blockIdx.x, blockIdx.y, Xc, ldc, nrhs, smem_d);
 }
 
 // T_b = tscale .* (sum of the block's item partials, in item order): one
@@ -885,15 +896,20 @@ __device__ void reduce_block(const KParams& kp, const BlockDesc& bd, int o, int 
 }
 
 template <typename AT>
-__global__ __launch_bounds__(256) void k_reduce_w(KParams kp, int nrhs) {
-    const BlockDesc bd = kp.blocks[blockIdx.x];
+__device__ void run_reduce_w(const KParams& kp, int block, int yg, int nrhs) {
+    const BlockDesc bd = kp.blocks[block];
     const int total = bd.rank * nrhs;
-    const int o = blockIdx.y * 256 + threadIdx.x;
+    const int o = yg * 256 + threadIdx.x;
     if (o >= total) return;
     if (bd.fmt == F64)
         reduce_block<double>(kp, bd, o, total, nrhs);
     else
         reduce_block<AT>(kp, bd, o, total, nrhs);
+}
+
+template <typename AT>
+__global__ __launch_bounds__(256) void k_reduce_w(KParams kp, int nrhs) {
+    run_reduce_w<AT>(kp, blockIdx.x, blockIdx.y, nrhs);
 }
 
 // rows [j0, j0 + rows) of T_b (stored [j][c], ld nrhs) for right-hand
@@ -1074,17 +1090,15 @@ __device__ __forceinline__ void leaf_mma(const XT* xs, const LeafD& d, int g, in
 // rest of lds_bytes it is staged once, before the leaf GEMM, and the levels
 // need no barrier; otherwise it goes through jc-row chunks.
 template <typename XT, typename AT, int NT>
-__global__ __launch_bounds__(kThreads) void k_expand_w(KParams kp, const XT* __restrict__ Xw, int64_t ldw,
-                                                       XT* __restrict__ Y, int64_t ldy, int nrhs, int lds_bytes,
-                                                       int jc) {
-    extern __shared__ double smem_d[];
-    __shared__ int s_off[kMaxDepth + 2];
+__device__ void run_expand_w(const KParams& kp, int tile, int yg, const XT* __restrict__ Xw, int64_t ldw,
+                             XT* __restrict__ Y, int64_t ldy, int nrhs, int lds_bytes, int jc, double* smem_d,
+                             int* s_off) {
     using MD = Mfma<double>;
     constexpr int CW = 16 * NT;
     constexpr int TS = CW + 4;
-    const ETile t = kp.etiles[blockIdx.x];
+    const ETile t = kp.etiles[tile];
     const LeafDesc L = kp.leaves[t.leaf];
-    const int c0 = blockIdx.y * CW;
+    const int c0 = yg * CW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, g = lane >> 4;
     const int r0 = 32 * wave + li, r1 = r0 + 16;        // tile rows of the lane's A operands
@@ -1202,6 +1216,15 @@ __global__ __launch_bounds__(kThreads) void k_expand_w(KParams kp, const XT* __r
 }
 
 template <typename XT, typename AT, int NT>
+__global__ __launch_bounds__(kThreads) void k_expand_w(KParams kp, const XT* __restrict__ Xw, int64_t ldw,
+                                                       XT* __restrict__ Y, int64_t ldy, int nrhs, int lds_bytes,
+                                                       int jc) {
+    extern __shared__ double smem_d[];
+    __shared__ int s_off[kMaxDepth + 2];
+    run_expand_w<XT, AT, NT>(kp, blockIdx.x, blockIdx.y, Xw, ldw, Y, ldy, nrhs, lds_bytes, jc, smem_d, s_off);
+}
+
+template <typename XT, typename AT, int NT>
 hipError_t launch_wide_nt(const KParams& kp, const XT* Xw, int64_t ldw, XT* Y, int64_t ldy, int nrhs,
                           const Timer& tm) {
     hipStream_t s = tm.s;
@@ -1259,6 +1282,136 @@ hipError_t launch_wide(const KParams& kp, const void* Xv, int64_t ldx, void* Yv,
     return launch_wide_nt<XT, AT, 8>(kp, Xw, ldw, Y, ldy, nrhs, tm);
 }
 
+// ---------------------------------------------------------------------------
+// batched products: persistent kernels over a work list of many operators
+// ---------------------------------------------------------------------------
+// Each workgroup walks the list with stride gridDim.x (the list is sorted by
+// the planner, longest first by default); every step runs the same device
+// code as the single-operator launch for one (operator, unit) pair.  A
+// barrier separates steps that use LDS.
+template <typename XT>
+__global__ __launch_bounds__(256) void kb_padx(const BatchOp* __restrict__ ops, const WorkItem* __restrict__ w,
+                                               int nw) {
+    for (int i = blockIdx.x; i < nw; i += gridDim.x) {
+        const WorkItem wi = w[i];
+        const BatchOp& o = ops[wi.op];
+        padx_leaf<XT>(o.kp, wi.idx, static_cast<const XT*>(o.X), o.ldx, o.nrhs);
+    }
+}
+
+template <typename XT, typename AT, int RG>
+__global__ __launch_bounds__(kThreads, HODLR_CONTRACT_MINW) void kb_contract(const BatchOp* __restrict__ ops,
+                                                                            const WorkItem* __restrict__ w, int nw,
+                                                                            int stage_cap) {
+    extern __shared__ double smem_d[];
+    __shared__ int s_flag;
+    for (int i = blockIdx.x; i < nw; i += gridDim.x) {
+        const WorkItem wi = w[i];
+        const BatchOp& o = ops[wi.op];
+        run_contract<XT, AT, RG>(o.kp, wi.idx, static_cast<const XT*>(o.Xc), o.ldc, o.nrhs,
+                                 reinterpret_cast<unsigned char*>(smem_d), &s_flag, stage_cap);
+        __syncthreads();
+    }
+}
+
+template <typename XT, typename AT, int RG, int RPL>
+__global__ __launch_bounds__(kThreads, HODLR_EXPAND_MINW) void kb_expand(const BatchOp* __restrict__ ops,
+                                                                        const WorkItem* __restrict__ w, int nw) {
+    extern __shared__ double smem_d[];
+    __shared__ int s_off[kMaxDepth + 1];
+    for (int i = blockIdx.x; i < nw; i += gridDim.x) {
+        const WorkItem wi = w[i];
+        const BatchOp& o = ops[wi.op];
+        run_expand<XT, AT, RG, RPL>(o.kp, wi.idx, static_cast<const XT*>(o.X), o.ldx, static_cast<XT*>(o.Y), o.ldy,
+                                    o.nrhs, reinterpret_cast<unsigned char*>(smem_d), s_off);
+        __syncthreads();
+    }
+}
+
+template <typename XT, typename AT, int NT>
+__global__ __launch_bounds__(kThreads) void kb_contract_w(const BatchOp* __restrict__ ops,
+                                                          const WorkItem* __restrict__ w, int nw) {
+    extern __shared__ double smem_d[];
+    for (int i = blockIdx.x; i < nw; i += gridDim.x) {
+        const WorkItem wi = w[i];
+        const BatchOp& o = ops[wi.op];
+        run_contract_w<XT, AT, NT>(o.kp, wi.idx, wi.y, static_cast<const XT*>(o.Xc), o.ldc, o.nrhs, smem_d);
+        __syncthreads();
+    }
+}
+
+template <typename AT>
+__global__ __launch_bounds__(256) void kb_reduce_w(const BatchOp* __restrict__ ops, const WorkItem* __restrict__ w,
+                                                   int nw) {
+    for (int i = blockIdx.x; i < nw; i += gridDim.x) {
+        const WorkItem wi = w[i];
+        const BatchOp& o = ops[wi.op];
+        run_reduce_w<AT>(o.kp, wi.idx, wi.y, o.nrhs);
+    }
+}
+
+template <typename XT, typename AT, int NT>
+__global__ __launch_bounds__(kThreads) void kb_expand_w(const BatchOp* __restrict__ ops,
+                                                        const WorkItem* __restrict__ w, int nw, int lds_bytes,
+                                                        int jc) {
+    extern __shared__ double smem_d[];
+    __shared__ int s_off[kMaxDepth + 2];
+    for (int i = blockIdx.x; i < nw; i += gridDim.x) {
+        const WorkItem wi = w[i];
+        const BatchOp& o = ops[wi.op];
+        run_expand_w<XT, AT, NT>(o.kp, wi.idx, wi.y, static_cast<const XT*>(o.Xc), o.ldc, static_cast<XT*>(o.Y),
+                                 o.ldy, o.nrhs, lds_bytes, jc, smem_d, s_off);
+        __syncthreads();
+    }
+}
+
+template <typename XT, typename AT, int RG>
+hipError_t batch_narrow(const BatchGroup& g, hipStream_t s) {
+    if (g.n_padx)
+        hipLaunchKernelGGL((kb_padx<XT>), dim3(g.grid[0]), dim3(256), 0, s, g.ops, g.padx, g.n_padx);
+    if (g.n_contract)
+        hipLaunchKernelGGL((kb_contract<XT, AT, RG>), dim3(g.grid[1]), dim3(kThreads), size_t(g.lds_contract), s,
+                           g.ops, g.contract, g.n_contract, g.stage_cap);
+    if (g.n_expand)
+        hipLaunchKernelGGL((kb_expand<XT, AT, RG, kRPL>), dim3(g.grid[3]), dim3(kThreads), size_t(g.lds_expand), s,
+                           g.ops, g.expand, g.n_expand);
+    return hipGetLastError();
+}
+
+template <typename XT, typename AT, int NT>
+hipError_t batch_wide(const BatchGroup& g, hipStream_t s) {
+    constexpr int NTC = NT > 4 ? 4 : NT;                // as the single-operator launch
+    if (g.n_padx)
+        hipLaunchKernelGGL((kb_padx<XT>), dim3(g.grid[0]), dim3(256), 0, s, g.ops, g.padx, g.n_padx);
+    if (g.n_contract)
+        hipLaunchKernelGGL((kb_contract_w<XT, AT, NTC>), dim3(g.grid[1]), dim3(kThreads), size_t(g.lds_contract), s,
+                           g.ops, g.contract, g.n_contract);
+    if (g.n_reduce)
+        hipLaunchKernelGGL((kb_reduce_w<AT>), dim3(g.grid[2]), dim3(256), 0, s, g.ops, g.reduce, g.n_reduce);
+    if (g.n_expand)
+        hipLaunchKernelGGL((kb_expand_w<XT, AT, NT>), dim3(g.grid[3]), dim3(kThreads), size_t(g.lds_expand), s,
+                           g.ops, g.expand, g.n_expand, int(g.lds_expand), g.jc);
+    return hipGetLastError();
+}
+
+template <typename XT, typename AT>
+hipError_t batch_typed(const BatchGroup& g, hipStream_t s) {
+    if (!g.wide) {
+        switch (g.rg) {
+            case 1: return batch_narrow<XT, AT, 1>(g, s);
+            case 2: return batch_narrow<XT, AT, 2>(g, s);
+            case 4: return batch_narrow<XT, AT, 4>(g, s);
+            default: return batch_narrow<XT, AT, 8>(g, s);
+        }
+    }
+    switch (g.rg) {
+        case 1: return batch_wide<XT, AT, 1>(g, s);
+        case 2: return batch_wide<XT, AT, 2>(g, s);
+        case 4: return batch_wide<XT, AT, 4>(g, s);
+        default: return batch_wide<XT, AT, 8>(g, s);
+    }
+}
+
 }  // namespace
 
 int launch_matvec(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs,
@@ -1279,6 +1432,59 @@ int launch_matvec(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_
         e = acc_double ? launch_rg<float, double>(kp, X, ldx, Y, ldy, nrhs, tm)
                        : launch_rg<float, float>(kp, X, ldx, Y, ldy, nrhs, tm);
     }
+    return int(e);
+}
+
+
+int plan_launch(const KParams& kp, const void* X, int64_t ldx, int nrhs, bool xy_double, bool acc_double,
+                OpLaunch* out) {
+    OpLaunch o{};
+    const size_t acc_bytes = acc_double ? 8 : 4;
+    const size_t xbytes = xy_double ? 8 : 4;
+    if (nrhs < kWideMin) {
+        int rg = nrhs == 1 ? 1 : nrhs == 2 ? 2 : nrhs <= 4 ? 4 : 8;
+        while (rg > 1 && lds_expand(kp, rg, acc_bytes) > kMaxLds) rg /= 2;
+        if (lds_expand(kp, rg, acc_bytes) > kMaxLds) return int(hipErrorInvalidConfiguration);
+        o.wide = 0;
+        o.rg = rg;
+        o.padx = kp.padded && kp.ncitems > 0;
+        o.stage_cap = stage_cap(kp, rg);
+        o.lds_contract = int64_t(o.stage_cap) * 8;
+        o.lds_expand = int64_t(lds_expand(kp, rg, acc_bytes));
+    } else {
+        const int nt = nrhs <= 16 ? 1 : nrhs <= 32 ? 2 : (nrhs <= 64 || xy_double) ? 4 : 8;
+        const int ntc = nt > 4 ? 4 : nt;
+        const int cw = 16 * nt;
+        const bool aligned = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((ldx * int64_t(xbytes)) % 16 == 0);
+        o.wide = 1;
+        o.rg = nt;
+        o.ntc = ntc;
+        o.padx = kp.padded || !aligned;
+        o.lds_contract = int64_t(kWaves) * ntc * 256 * 8;
+        const int64_t xb = 2 * int64_t(cw) * kXLD * int64_t(xbytes);
+        const int64_t all = int64_t(kp.max_tstage) * (cw + 4);
+        const int64_t ch32 = int64_t(32) * (cw + 4) * 8, ch16 = ch32 / 2;
+        o.jc = 0;
+        o.lds_expand = xb + all;
+        if (o.lds_expand > kMaxLds) {
+            o.jc = xb + ch32 <= kMaxLds ? 32 : 16;
+            o.lds_expand = xb + (o.jc == 32 ? ch32 : ch16);
+            if (o.lds_expand > kMaxLds) return int(hipErrorInvalidConfiguration);
+        }
+        o.gy_contract = (nrhs + 16 * ntc - 1) / (16 * ntc);
+        o.gy_expand = (nrhs + cw - 1) / cw;
+    }
+    *out = o;
+    return 0;
+}
+
+int launch_batch_group(const BatchGroup& g, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (g.xy_double)
+        e = g.acc_double ? batch_typed<double, double>(g, s) : batch_typed<double, float>(g, s);
+    else
+        e = g.acc_double ? batch_typed<float, double>(g, s) : batch_typed<float, float>(g, s);
     return int(e);
 }
 

@@ -166,6 +166,19 @@ def test_edge_cases_depth0_n1_rank0_empty_leaves():
     _run(case3, h3, ["fp32", "fp16"], 16, "fp32", "fp32", "empty-leaves-wide")
 
 
+@pytest.mark.parametrize("nrhs", [16, 40])
+def test_wide_large_leaves(nrhs):
+    """Leaves of 1024 rows (eight 128-row expansion tiles per leaf, V chunks
+    of several items per block) on the matrix-core path, fp32 and fp64."""
+    case = Case("c2_s", n=4096, depth=2, eps=1e-5)
+    h = case.library_op()
+    h.assign_precision(case.eps, case.cfg.allowed, case.norms2)
+    fm = [lv[0] for lv in h.levels()]
+    _run(case, h, fm, nrhs, "fp32", "fp32", "large-leaves")
+    h.set_level_precisions(["fp64", "e4m3"], H.ACC_FP64)
+    _run(case, h, ["fp64", "e4m3"], nrhs, "fp64", "fp64", "large-leaves-fp64")
+
+
 @pytest.mark.parametrize("nrhs", [5, 20])
 def test_strided_unaligned_x_and_y(nrhs):
     """ld of X and Y not a multiple of 4 elements (unpadded operator): the

@@ -193,6 +193,22 @@ def test_error_paths_are_reported_not_raised_in_c():
     with pytest.raises(H.HodlrError):
         h.block(h.nblocks)
     assert H.lib().hodlr_status_string(5) == b"HODLR_E_RANGE"
+    # batched: argument checks come before any device work
+    import ctypes
+    L = H.lib()
+    one = (ctypes.c_void_p * 1)(h.handle.value)
+    ptr = (ctypes.c_void_p * 1)(1)
+    ld = np.array([c.n], dtype=np.int64)
+    nr = np.array([1], dtype=np.int32)
+    dt = np.array([1], dtype=np.int32)
+    args = (ctypes.cast(ptr, ctypes.c_void_p), H._lib._ptr(ld), ctypes.cast(ptr, ctypes.c_void_p),
+            H._lib._ptr(ld), H._lib._ptr(nr), H._lib._ptr(dt), None)
+    assert L.hodlr_matvec_batched(ctypes.cast(one, ctypes.c_void_p), 1, *args) == 2      # host-only handle
+    assert L.hodlr_matvec_batched(ctypes.cast(one, ctypes.c_void_p), -1, *args) == 1     # count < 0
+    assert L.hodlr_matvec_batched(ctypes.cast(one, ctypes.c_void_p), 0, *args) == 0      # empty batch
+    bad = np.array([0], dtype=np.int32)
+    assert L.hodlr_matvec_batched(ctypes.cast(one, ctypes.c_void_p), 1, args[0], args[1], args[2], args[3],
+                                  H._lib._ptr(bad), args[5], None) in (1, 2)
 
 
 def test_depth_zero_and_rank_zero_operators():
