@@ -44,7 +44,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_expand_c2_nrhs1.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_nrhs1.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2407_21637_amd", "csrc", "kernels.hip")
 
 
@@ -85,8 +85,9 @@ SBYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2, "e4m3": 1, "e5m2": 1}
 
 
 def work(h, n, nrhs, xy_bytes):
-    """Algorithmic bytes and flops of one product; bytes of the expansion and
-    contraction launches; fp64 flops of the leaf products."""
+    """Algorithmic bytes and flops of one product; algorithmic bytes of the
+    second (expansion) and first (contraction, with the leaf tiles on the wave
+    path) launches; fp64 flops of the leaf products."""
     inf = h.info()
     B = inf["leaf_bytes"] + inf["factor_bytes"] + inf["scale_bytes"] + n * nrhs * 2 * xy_bytes
     lr = ub = vb = 0
@@ -97,24 +98,29 @@ def work(h, n, nrhs, xy_bytes):
         ub += bi["nrows"] * bi["rank"] * s
         vb += bi["ncols"] * bi["rank"] * s
     F = 2 * nrhs * (inf["leaf_bytes"] // 8 + lr)
-    expand = inf["leaf_bytes"] + ub + n * nrhs * 2 * xy_bytes
-    contract = vb + n * nrhs * xy_bytes
     leaf_flops = 2 * nrhs * (inf["leaf_bytes"] // 8)
-    return B, F, expand, contract, leaf_flops
+    if nrhs >= 8:       # matrix-core path: contraction | expansion with the leaf GEMM
+        first = vb + n * nrhs * xy_bytes
+        second = inf["leaf_bytes"] + ub + n * nrhs * 2 * xy_bytes
+    else:               # wave path: contraction and leaf GEMV tiles | expansion
+        first = inf["leaf_bytes"] + vb + n * nrhs * xy_bytes
+        second = ub + n * nrhs * xy_bytes
+    return B, F, second, first, leaf_flops
 
 
-def time_steps(h, X, Y, steps, warmup, torch):
-    """ms per product: K products captured in one HIP graph, replayed."""
+def time_steps(fn, steps, warmup, torch):
+    """ms per product: K calls of fn (one product each, on the current
+    stream) captured in one HIP graph, replayed."""
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        for _ in range(max(warmup, 1)):     # also sizes this stream's workspace
-            h.matvec(X, Y)
+        for _ in range(max(warmup, 1)):     # also sizes this stream's workspace (and plans a batch)
+            fn()
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
         for _ in range(steps):
-            h.matvec(X, Y)
+            fn()
     torch.cuda.synchronize()
     g.replay()                              # untimed: first replay of the graph
     torch.cuda.synchronize()
@@ -144,15 +150,15 @@ def time_phases(h, X, Y, reps, torch):
     return {k: v[0] / v[1] * 1e3 for k, v in ph.items() if v[1]}
 
 
-def time_cold(h, X, Y, reps, torch):
+def time_cold(fn, reps, torch):
     """Per-product time with the caches flushed (1 GiB written) before each."""
-    flush = torch.empty(1 << 28, dtype=torch.float32, device=X.device)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
     out = []
     for _ in range(reps):
         flush.zero_()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        h.matvec(X, Y)
+        fn()
         e1.record()
         torch.cuda.synchronize()
         out.append(e0.elapsed_time(e1))
@@ -187,6 +193,139 @@ def cpu_baseline(cfg, blocks, leaves, op, level_fmt, B_alg, X, budget_s=12.0):
                       f"on the same stored operator, {sec * 1e3:.1f} ms each"}, y, U, V, oblocks, lb
 
 
+def build_batch(name):
+    """Compress a batched workload over the library's partitions (host, untimed)."""
+    from hodlr_inputs import batch as BT
+    import paper_2407_21637_amd as H
+    specs = BT.get(name)
+    parts = []
+    for sp in specs:
+        desc = H.tree_blocks(sp.n, sp.depth)
+        lb = H.tree_bounds(sp.n, sp.depth)[sp.depth]
+        parts.append(([tuple(int(v) for v in d[1:]) for d in desc],
+                      [(int(lb[i]), int(lb[i + 1] - lb[i])) for i in range(len(lb) - 1)]))
+    t = time.time()
+    ops = BT.build_all(specs, parts, log=log)
+    log(f"[bench] compressed {name}: {len(specs)} operators, sum n = {sum(sp.n for sp in specs)} "
+        f"in {time.time() - t:.1f}s")
+    return specs, parts, ops
+
+
+def main_batch(args, torch, H):
+    """The batched workload: all operators in one hodlr_matvec_batched call."""
+    from hodlr_inputs import batch as BT
+    specs, parts, cops = args.batch_ops
+    dev = torch.device("cuda:0")
+    t = time.time()
+    hs, Xs, Ys, xbs = [], [], [], []
+    for sp, c in zip(specs, cops):
+        h = H.Operator(sp.n, sp.depth, c.leaves, c.U, c.V, device=0)
+        h.assign_precision(sp.eps, BT.ALLOWED, np.concatenate([[c.norm2_all], c.norm2_blocks]))
+        dt = torch.float64 if sp.x_dtype == "fp64" else torch.float32
+        X = H.colmajor_empty(sp.n, sp.nrhs, dt, dev)
+        X.copy_(torch.from_numpy(np.asfortranarray(sp.X())).to(dt))
+        hs.append(h)
+        Xs.append(X)
+        Ys.append(H.colmajor_empty(sp.n, sp.nrhs, dt, dev))
+        xbs.append(8 if sp.x_dtype == "fp64" else 4)
+    log(f"[bench] {len(hs)} operators on GPU in {time.time() - t:.1f}s")
+
+    def fn():
+        H.matvec_batched(hs, Xs, Ys)
+
+    t = time.time()
+    fn()                                   # plan: work lists, autotuning, graph
+    torch.cuda.synchronize()
+    log(f"[bench] batch plan built and tuned in {time.time() - t:.2f}s")
+
+    def totals():
+        B = F = 0
+        for h, sp, xb in zip(hs, specs, xbs):
+            w = work(h, sp.n, sp.nrhs, xb)
+            B += w[0]
+            F += w[1]
+        return B, F
+
+    B, F = totals()
+    ms = time_steps(fn, args.steps, args.warmup, torch)
+    if args.profile_run:
+        print(json.dumps({"profile_run": True, "us_per_step": ms * 1e3}), flush=True)
+        return
+    cold = time_cold(fn, 5, torch)
+    log(f"[bench] batch: {ms * 1e3:.1f} us/step, {B / ms / 1e6:.1f} GB/s, cold {cold * 1e3:.1f} us")
+    fm = [[lv[0] for lv in h.levels()] for h in hs]
+    acc = [h.info()["acc_dtype"] for h in hs]
+    # uniform fp64 on the same GPU (same ranks), then back
+    for h, sp in zip(hs, specs):
+        h.set_level_precisions(["fp64"] * sp.depth, H.ACC_FP64)
+    B64, _ = totals()
+    ms64 = time_steps(fn, args.steps, args.warmup, torch)
+    for h, sp, c in zip(hs, specs, cops):
+        h.assign_precision(sp.eps, BT.ALLOWED, np.concatenate([[c.norm2_all], c.norm2_blocks]))
+    log(f"[bench] uniform fp64 batch: {ms64 * 1e3:.1f} us/step")
+    value = B / (ms * 1e-3) / 1e9
+    fmt_count = {}
+    for f in fm:
+        for x in f:
+            fmt_count[x] = fmt_count.get(x, 0) + 1
+    out = {
+        "metric": "HODLR matvec GB/s & Gflop/s (% roofline); speedup mixed vs FP64 at fixed eps",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {len(specs)} independent operators, n log-uniform, kernels "
+                               f"1/(r+1e-3), exp(-r), exp(-r^2/0.08) in 1D/2D, eps 1e-4/1e-6/1e-8, nrhs 1/8/32, "
+                               f"one hodlr_matvec_batched call", "operators": len(specs),
+                   "sum_n": int(sum(sp.n for sp in specs)), "level_formats": fmt_count,
+                   "fp64_accumulation_ops": int(sum(a == "fp64" for a in acc))},
+        "gflops": round(F / (ms * 1e-3) / 1e9, 2), "hbm_frac": round(value / HBM_PEAK_GBS, 4),
+        "alg_bytes": int(B), "alg_flops": int(F),
+        "cold_cache_gbs": round(B / (cold * 1e-3) / 1e9, 2),
+        "speedup_vs_fp64": round(ms64 / ms, 3), "fp64_gbs": round(B64 / (ms64 * 1e-3) / 1e9, 2),
+        "roofline": {"bound": "hbm", "kernel": "whole batch (persistent launches of every kernel variant)",
+                     "achieved": round(value, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(value / HBM_PEAK_GBS, 4), "traffic": None,
+                     "alg_bytes_per_launch": int(B), "mean_launch_us": round(ms * 1e3, 2)},
+    }
+    if not args.no_cpu:
+        from oracle import bounds as BD
+        from oracle import matvec as MV
+        from oracle import quantize as Q
+        from oracle import tree as T
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:  # pragma: no cover
+            threads = 1
+        fn()
+        torch.cuda.synchronize()
+        worst, done_b, t_cpu, k = 0.0, 0, 0.0, 0
+        for k, (h, sp, c, xb) in enumerate(zip(hs, specs, cops, xbs)):
+            blocks = T.blocks(sp.n, sp.depth)
+            lb = T.leaves(sp.n, sp.depth)
+            U = [Q.quantize(u, fm[k][b.level - 1]).values for b, u in zip(blocks, c.U)]
+            V = [Q.quantize(v, fm[k][b.level - 1]).values for b, v in zip(blocks, c.V)]
+            X = sp.X()
+            t0 = time.perf_counter()
+            y = MV.matvec(sp.n, blocks, lb, c.leaves, U, V, X)
+            t_cpu += time.perf_counter() - t0
+            done_b += work(h, sp.n, sp.nrhs, xb)[0]
+            z = MV.matvec_abs(sp.n, blocks, lb, c.leaves, U, V, X)
+            M = BD.chain_length(blocks, c.ranks, [m for _, m in lb], sp.depth)
+            u_acc = 2.0 ** -24 if acc[k] == "fp32" else 2.0 ** -53
+            tau = BD.tolerance_prob(z, y, M, u_acc, 2.0 ** -24 if xb == 4 else 2.0 ** -53)
+            err = np.abs(Ys[k].cpu().double().numpy() - y)
+            worst = max(worst, float((err / tau).max()))
+            if t_cpu >= 12.0:
+                break
+        out["cpu_baseline"] = {"value": round(done_b / t_cpu / 1e9, 4), "unit": "GB/s", "cores": int(threads),
+                               "kind": "oracle",
+                               "sample": f"the oracle's fp64 HODLR_MATVEC of the first {k + 1} operators of the "
+                                         f"batch (same stored operators and X), {t_cpu:.1f} s in total"}
+        out["check"] = {"max_err_over_tau_prob": worst, "operators_checked": k + 1}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,9 +345,17 @@ def main():
                                    "run with --gpus 1"}), flush=True)
         sys.exit(2)
 
+    # torch first: the library then binds to the HIP runtime torch loaded
     import torch
     import paper_2407_21637_amd as H
     from hodlr_inputs import configs as CF
+    from hodlr_inputs.batch import BATCHES
+
+    batch_ops = None
+    if args.workload in BATCHES and not args.copy_calibration:
+        # host-side, in spawned processes, before anything touches the GPU
+        batch_ops = build_batch(args.workload)
+    args.batch_ops = batch_ops
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
@@ -221,6 +368,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "copies": 5}), flush=True)
         return
     H.lib()   # fail loudly if the HIP library is not built
+    if args.workload in BATCHES:
+        return main_batch(args, torch, H)
     dev = torch.device("cuda:0")
     cfg = CF.get(args.workload)
     nrhs0 = args.nrhs if args.nrhs is not None else cfg.nrhs[0]
@@ -243,9 +392,9 @@ def main():
         X.copy_(torch.from_numpy(np.asfortranarray(Xh[:, :nrhs])).to(xdt))
         Y = H.colmajor_empty(cfg.n, nrhs, xdt, dev)
         B, Fl, EB, CB, LF = work(h, cfg.n, nrhs, xb)
-        ms = time_steps(h, X, Y, args.steps, args.warmup, torch)
+        ms = time_steps(lambda: h.matvec(X, Y), args.steps, args.warmup, torch)
         ph = time_phases(h, X, Y, 50, torch)
-        cold = time_cold(h, X, Y, 10, torch)
+        cold = time_cold(lambda: h.matvec(X, Y), 10, torch)
         results[nrhs] = dict(ms=ms, phases=ph, B=B, F=Fl, EB=EB, CB=CB, LF=LF, cold_ms=cold, X=X, Y=Y)
         log(f"[bench] nrhs={nrhs}: {ms * 1e3:.1f} us/step, {B / ms / 1e6:.1f} GB/s, {Fl / ms / 1e9:.2f} Tflop/s, "
             f"cold {cold * 1e3:.1f} us, kernels (us) {ph}")
@@ -256,22 +405,23 @@ def main():
     # uniform-fp64 product on the same GPU, same ranks
     r = results[nrhs0]
     h.set_level_precisions(["fp64"] * cfg.depth, H.ACC_FP64)
-    ms64 = time_steps(h, r["X"], r["Y"], args.steps, args.warmup, torch)
+    ms64 = time_steps(lambda: h.matvec(r["X"], r["Y"]), args.steps, args.warmup, torch)
     B64 = work(h, cfg.n, nrhs0, xb)[0]
     h.assign_precision(cfg.eps, cfg.allowed, norms2)
     log(f"[bench] uniform fp64: {ms64 * 1e3:.1f} us/step")
 
     exp_us = r["phases"]["expand"]
     con_us = r["phases"].get("contract", 0.0)
+    wide = nrhs0 >= 8
     traffic = traffic_c = None
     tr = read_traffic()
     if tr.get("kernel_sha") == kernel_hash() and tr.get("workload") == cfg.name and \
-            tr.get("nrhs") == str(nrhs0) and "k_expand_bytes_per_launch" in tr:
-        traffic = int(tr["k_expand_bytes_per_launch"])
-        traffic_c = int(tr.get("k_contract_bytes_per_launch", 0)) or None
+            tr.get("nrhs") == str(nrhs0):
+        traffic = int(tr.get("second_launch_bytes", 0)) or None
+        traffic_c = int(tr.get("first_launch_bytes", 0)) or None
     value = r["B"] / (r["ms"] * 1e-3) / 1e9
-    wide = nrhs0 >= 16
     exp_gbs = r["EB"] / (exp_us * 1e-6) / 1e9
+    con_gbs = r["CB"] / (con_us * 1e-6) / 1e9 if con_us else 0.0
     if wide:
         # matrix-core path: the fp64 leaf GEMM dominates the expansion's work
         achieved = r["LF"] / (exp_us * 1e-6) / 1e12
@@ -281,10 +431,11 @@ def main():
                 "alg_flops_per_launch": int(r["LF"]), "alg_bytes_per_launch": int(r["EB"]),
                 "hbm_gbs": round(exp_gbs, 2), "mean_launch_us": round(exp_us, 2)}
     else:
-        roof = {"bound": "hbm", "kernel": "k_expand (fp64 leaf GEMV + expansion, writes Y)",
-                "achieved": round(exp_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(exp_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "alg_bytes_per_launch": int(r["EB"]), "mean_launch_us": round(exp_us, 2)}
+        # wave path: the first launch (contraction items + fp64 leaf GEMV tiles) moves most bytes
+        roof = {"bound": "hbm", "kernel": "k_phase1 (contraction items + fp64 leaf GEMV tiles)",
+                "achieved": round(con_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(con_gbs / HBM_PEAK_GBS, 4), "traffic": traffic_c,
+                "alg_bytes_per_launch": int(r["CB"]), "mean_launch_us": round(con_us, 2)}
     out = {
         "metric": "HODLR matvec GB/s & Gflop/s (% roofline); speedup mixed vs FP64 at fixed eps",
         "value": round(value, 2),
@@ -311,9 +462,11 @@ def main():
         "fp64_gbs": round(B64 / (ms64 * 1e-3) / 1e9, 2),
         "kernels_us": {k: round(v, 2) for k, v in r["phases"].items()},
         "roofline": roof,
-        "contract_kernel": {"alg_bytes_per_launch": int(r["CB"]), "mean_launch_us": round(con_us, 2),
-                            "achieved_gbs": round(r["CB"] / (con_us * 1e-6) / 1e9, 2) if con_us else None,
-                            "traffic": traffic_c},
+        "launches": {
+            "first": {"kernel": "k_contract_w" if wide else "k_phase1", "alg_bytes": int(r["CB"]),
+                      "mean_us": round(con_us, 2), "achieved_gbs": round(con_gbs, 2), "traffic": traffic_c},
+            "second": {"kernel": "k_expand_w" if wide else "k_expand", "alg_bytes": int(r["EB"]),
+                       "mean_us": round(exp_us, 2), "achieved_gbs": round(exp_gbs, 2), "traffic": traffic}},
     }
     for k in nrhs_list[1:]:
         rk = results[k]
@@ -321,7 +474,7 @@ def main():
                            "gflops": round(rk["F"] / (rk["ms"] * 1e-3) / 1e9, 2),
                            "ms_per_step": round(rk["ms"], 5),
                            "kernels_us": {q: round(v, 2) for q, v in rk["phases"].items()}}
-        if k >= 16 and "expand" in rk["phases"]:
+        if k >= 8 and "expand" in rk["phases"]:
             out[f"nrhs{k}"]["leaf_fp64_mfma_tflops"] = round(rk["LF"] / (rk["phases"]["expand"] * 1e-6) / 1e12, 3)
     if not args.no_cpu:
         Xc = Xh[:, :nrhs0]

@@ -88,8 +88,38 @@ def get(name: str) -> list[OpSpec]:
     return specs(**BATCHES[name])
 
 
-def build(spec: OpSpec, blocks, leaves, seed: int = 12345):
+def build(spec: OpSpec, blocks, leaves, seed: int = 12345, workers=None):
     """Points and the compressed operator of one spec over the caller's partition."""
     from .compress import compress
     P = spec.points()
-    return P, compress(spec.kernel, P, blocks, leaves, spec.eps, "frob", seed=seed)
+    return P, compress(spec.kernel, P, blocks, leaves, spec.eps, "frob", seed=seed, workers=workers)
+
+
+def _build_one(args):
+    spec, blocks, leaves = args
+    return build(spec, blocks, leaves, workers=1)[1]
+
+
+def build_all(specs, parts, processes=None, log=None):
+    """Compressed operators of every spec, one process per operator at a
+    time (``parts``: (blocks, leaves) per spec, the caller's partitions).
+    Uses spawned processes: call it before the GPU is touched."""
+    import multiprocessing as mp
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+    if processes is None:
+        try:
+            processes = max(1, min(16, len(os.sched_getaffinity(0))))
+        except AttributeError:  # pragma: no cover
+            processes = max(1, min(16, os.cpu_count() or 1))
+    out = [None] * len(specs)
+    jobs = [(s, b, l) for s, (b, l) in zip(specs, parts)]
+    order = sorted(range(len(specs)), key=lambda i: -specs[i].n)       # largest first
+    with ProcessPoolExecutor(processes, mp_context=mp.get_context("spawn")) as ex:
+        futs = {ex.submit(_build_one, jobs[i]): i for i in order}
+        from concurrent.futures import as_completed
+        for done, f in enumerate(as_completed(futs), 1):
+            out[futs[f]] = f.result()
+            if log and (done % 32 == 0 or done == len(specs)):
+                log(f"[batch] compressed {done}/{len(specs)} operators")
+    return out

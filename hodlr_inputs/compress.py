@@ -70,8 +70,8 @@ def _rank(s, eps, rule, nb2, norm_a_2, res2=0.0):
 
 
 class _Pool:
-    def __init__(self):
-        self.nw = _workers()
+    def __init__(self, workers=None):
+        self.nw = workers if workers else _workers()
         self.ex = ThreadPoolExecutor(self.nw)
 
     def map(self, fn, items):
@@ -138,11 +138,12 @@ def _random_block(kernel, P, b, eps, rule, norm_a_2, pool, rng, s0):
 
 
 def compress(kernel, P, blocks, leaves, eps, rule="frob", norm_a_2=None,
-             seed=12345, dense_limit=512 * 512) -> Compressed:
+             seed=12345, dense_limit=512 * 512, workers=None) -> Compressed:
     """Compress every off-diagonal block of the kernel matrix over ``P``.
 
     ``blocks``: (row0, nrows, col0, ncols) per off-diagonal block in the
-    library's canonical order; ``leaves``: (start, size) per leaf.
+    library's canonical order; ``leaves``: (start, size) per leaf;
+    ``workers``: threads (default: the usable cores, at most 16).
     """
     if rule == "spec_global" and norm_a_2 is None:
         raise ValueError("spec_global needs norm_a_2")
@@ -152,7 +153,7 @@ def compress(kernel, P, blocks, leaves, eps, rule="frob", norm_a_2=None,
     nb = len(blocks)
     U, S, Z, nb2 = [None] * nb, [None] * nb, [None] * nb, np.zeros(nb)
     sk = [0] * nb
-    pool = _Pool()
+    pool = _Pool(workers)
     rng = np.random.default_rng(seed)
     twin = {}                      # lower block j derived from upper block i
     if kernel.symmetric or kernel.antisymmetric:

@@ -179,8 +179,8 @@ hodlr_status hodlr_export_block(hodlr_op op, int32_t block, void* u_codes, int8_
 /* Y = A_H X (Alg. "HODLR_MATVEC").  xy_dtype is HODLR_FP32 or HODLR_FP64
  * for both X and Y.  Leaf products D_i X_i run in fp64; a level stored in
  * fp64 runs in fp64; other levels run in the accumulation precision, with
- * the stored codes converted in registers.  With nrhs < 16 the products
- * are wavefront reductions (HBM-bound); with nrhs >= 16 they run on the
+ * the stored codes converted in registers.  With nrhs < 8 the products
+ * are wavefront reductions (HBM-bound); with nrhs >= 8 they run on the
  * matrix cores (fp64 MFMA for leaves and fp64 levels, fp32 MFMA for the
  * others).  stream is a hipStream_t (NULL: the default stream).  The call
  * only enqueues work; on first use with a larger nrhs it may allocate (and
@@ -218,9 +218,9 @@ hodlr_status hodlr_matvec_batched(const hodlr_op* ops, int32_t count, const void
  * of this handle record a HIP event pair around each of their kernel phases
  * on the launch stream (0 turns recording off and drops the records).
  * Phases: 0 padded copy of X (when a leaf size is not a multiple of 16, or,
- * for nrhs >= 16, when X's columns are not 16-byte aligned), 1 contraction
+ * for nrhs >= 8, when X's columns are not 16-byte aligned), 1 contraction
  * (T = V^T X for every block), 2 expansion and leaves (Y = D X + U T),
- * 3 sum of the contraction's partial results into T (nrhs >= 16 only; below
+ * 3 sum of the contraction's partial results into T (nrhs >= 8 only; below
  * that the contraction's last workgroup per block does it inside phase 1).
  * hodlr_profile_read synchronises on the recorded
  * events and returns, per phase, the summed duration in milliseconds and

@@ -109,6 +109,7 @@ struct KParams {
     double* partial;             // workspace: sum over items of rank * nrhs
     double* T;                   // workspace: sum over blocks of rank * nrhs
     void* xpad;                  // workspace: padded copy of X (npad * nrhs), if needed
+    double* W;                   // workspace (nrhs < kWideMin): leaf products D_i X_i, npad * nrhs
     int32_t* sync;               // workspace: sync_words(nblocks) counters, zero between launches
     int64_t npad;                // padded rows
     int32_t max_leaf;            // largest leaf (rows)
@@ -131,6 +132,9 @@ struct KParams {
 constexpr int kSyncHead = 4;
 constexpr int64_t sync_words(int64_t nblocks) { return kSyncHead + nblocks; }
 
+// products with at least this many right-hand sides run on the matrix cores
+constexpr int kWideMin = 8;
+
 constexpr int kPhases = 4;     // padded X copy, contraction, expansion, reduction of partials
 
 // Launch the whole product on `stream`.  xy_double: X/Y are fp64 (else fp32);
@@ -148,7 +152,7 @@ int launch_matvec(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_
 // How one product of one operator is launched (chosen as the
 // single-operator path chooses it).
 struct OpLaunch {
-    int32_t wide;              // matrix-core path (nrhs >= 16)
+    int32_t wide;              // matrix-core path (nrhs >= kWideMin)
     int32_t rg;                // wave path: right-hand sides per pass; matrix-core path: 16-column tiles
     int32_t ntc;               // matrix-core contraction: 16-column tiles
     int32_t padx;              // X goes through the padded copy

@@ -222,8 +222,9 @@ struct Workspace {
     double* partial = nullptr;
     double* T = nullptr;
     void* xpad = nullptr;
+    double* W = nullptr;       // leaf products of the wave path
     int32_t* sync = nullptr;   // counters of the fused launch; zeroed once, self-resetting
-    int64_t cap_partial = 0, cap_T = 0, cap_xpad = 0, cap_sync = 0;
+    int64_t cap_partial = 0, cap_T = 0, cap_xpad = 0, cap_sync = 0, cap_W = 0;
     uint64_t gen = 0;          // bumped whenever a buffer is replaced (batched plans keep pointers)
 };
 
@@ -335,6 +336,7 @@ void free_device(hodlr_op_s* op) {
         dev_free(kv.second.partial);
         dev_free(kv.second.T);
         dev_free(kv.second.xpad);
+        dev_free(kv.second.W);
         dev_free(kv.second.sync);
     }
     op->ws.clear();
@@ -1007,9 +1009,9 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
     Workspace& w = op->ws[stream];
     const int64_t need_p = std::max<int64_t>(1, op->total_item_rank * nrhs);
     const int64_t need_t = std::max<int64_t>(1, op->total_rank * nrhs);
-    // padded X: when some leaf is padded, and for the matrix-core path (nrhs >= 16),
+    // padded X: when some leaf is padded, and for the matrix-core path (nrhs >= kWideMin),
     // which reads X with 16-byte vector loads and copies it when it is not aligned
-    const int64_t need_x = (op->padded || nrhs >= 16) ? op->npad * nrhs * (xy_double ? 8 : 4) : 0;
+    const int64_t need_x = (op->padded || nrhs >= kWideMin) ? op->npad * nrhs * (xy_double ? 8 : 4) : 0;
     auto grow = [&](void** ptr, int64_t* cap, int64_t bytes, const char* what) -> hodlr_status {
         if (bytes <= *cap) return HODLR_OK;
         if (*ptr) {
@@ -1034,6 +1036,9 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
         return r;
     if ((r = grow(reinterpret_cast<void**>(&w.T), &w.cap_T, need_t * 8, "T")) != HODLR_OK) return r;
     if (need_x && (r = grow(&w.xpad, &w.cap_xpad, need_x, "padded X")) != HODLR_OK) return r;
+    const int64_t need_w = nrhs < kWideMin ? op->npad * nrhs * 8 : 0;
+    if (need_w && (r = grow(reinterpret_cast<void**>(&w.W), &w.cap_W, need_w, "leaf products")) != HODLR_OK)
+        return r;
     const int64_t need_s = sync_words(op->nb) * int64_t(sizeof(int32_t));
     if (need_s > w.cap_sync) {
         if ((r = grow(reinterpret_cast<void**>(&w.sync), &w.cap_sync, need_s, "counters")) != HODLR_OK) return r;
@@ -1051,6 +1056,7 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
     kp->partial = w.partial;
     kp->T = w.T;
     kp->xpad = w.xpad;
+    kp->W = w.W;
     kp->sync = w.sync;
     kp->npad = op->npad;
     kp->max_leaf = op->max_leaf;
@@ -1190,6 +1196,11 @@ hodlr_status build_plan(const hodlr_op* ops, int count, const void* const* X, co
             const int64_t cost = int64_t(it.nr) * bd.rank * fmt_bytes(bd.fmt) + int64_t(it.nr) * 4 * s_rhs;
             for (int y = 0; y < gyc; ++y) gb.work[1].push_back({cost, WorkItem{oi, c, y, 0}});
         }
+        if (!ol.wide)             // the wave path's first launch also runs the leaf tiles (y = 1)
+            for (int t = 0; t < int(op->etiles.size()); ++t) {
+                const ETile& et = op->etiles[t];
+                gb.work[1].push_back({int64_t(et.nr) * op->ldesc[et.leaf].mp * 8, WorkItem{oi, t, 1, 0}});
+            }
         if (ol.wide && !op->citems.empty())
             for (int b = 0; b < op->nb; ++b) {
                 const int64_t total = int64_t(op->bdesc[b].rank) * nrhs[i];
@@ -1200,7 +1211,7 @@ hodlr_status build_plan(const hodlr_op* ops, int count, const void* const* X, co
         for (int t = 0; t < int(op->etiles.size()); ++t) {
             const ETile& et = op->etiles[t];
             const LeafDesc& L = op->ldesc[et.leaf];
-            int64_t cost = int64_t(et.nr) * L.mp * 8;
+            int64_t cost = ol.wide ? int64_t(et.nr) * L.mp * 8 : int64_t(et.nr) * 8;
             for (int k = 1; k <= op->depth; ++k) {
                 const BlockDesc& bd = op->bdesc[((1 << k) - 2) + (et.leaf >> (op->depth - k))];
                 cost += int64_t(et.nr) * bd.rank * fmt_bytes(bd.fmt);
@@ -1318,6 +1329,7 @@ hodlr_status tune_plan(BatchPlan* plan, int device, hipStream_t s) {
     return ok();
 }
 
+// The chosen launches, in order, captured on a private stream.
 hodlr_status capture_plan(BatchPlan* plan) {
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);

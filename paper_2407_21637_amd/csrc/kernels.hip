@@ -5,18 +5,25 @@
 //   b <- 0;  b_rows(b) += U_b (V_b^T x_cols(b)) for every off-diagonal block;
 //   b_i += D_i x_i for every leaf.
 //
-// Two launches per product (one kernel boundary is the only synchronisation
-// between the phases; no work queue, no spin-waits):
+// Wave path (nrhs < kWideMin = 8), two launches per product; one kernel boundary is
+// the only synchronisation between phases (no work queue, no spin-waits):
 //
-//  * k_contract, one workgroup per contraction item: item = rows [r0, r0+nr)
-//    of the V panel of one block; it stores the partial sums of
-//    T_b = V_b^T X over its rows and counts itself in the block's arrival
-//    counter.  The last item of a block to arrive adds the block's partials
-//    in item order (deterministic, no float atomics), applies the column
-//    scales, stores T_b and clears the counter for the next launch.
-//  * k_expand, one workgroup per expansion tile: tile = 64*RPL padded rows
-//    of one leaf.  It computes D_i X_i in fp64, adds U_b T_b for each of its
-//    depth ancestors' blocks, sums its waves' partial rows and writes Y once.
+//  * k_phase1: workgroups [0, ncitems) take contraction items, the others
+//    the leaf tiles.  A contraction item (rows [r0, r0+nr) of the V panel of
+//    one block) stores its partial sums of T_b = V_b^T X and counts itself
+//    in the block's arrival counter; the last item of a block to arrive
+//    adds the partials in item order (deterministic, no float atomics),
+//    applies the column scales, stores T_b and clears the counter for the
+//    next launch.  A leaf tile (64*RPL padded rows of one leaf) computes
+//    W = D_i X_i in fp64.  Neither waits for the other, so the V and D
+//    streams share the first launch.
+//  * k_expand, one workgroup per tile: Y rows = W + U_b T_b over the tile's
+//    depth ancestor blocks (each wave takes whole levels), the waves'
+//    partial rows are added in LDS and Y is written once.
+//
+// Matrix-core path (nrhs >= 8): k_contract_w, k_reduce_w, k_expand_w (see
+// the section "many right-hand sides").  Batched products run the same
+// device code from persistent kernels (section "batched products").
 //
 // Stored codes are converted in registers (Sect. 3.3: low-precision
 // storage cast to the working precision on the fly).
@@ -403,7 +410,6 @@ __device__ void expand_level(const KParams& kp, const BlockDesc& bd, int chunk0,
                              const double* __restrict__ ts, AT acc[RPL][RG]) {
     constexpr int S = Codec<F>::kBytes;
     constexpr int UN = sizeof(CT) == 8 ? kUnroll / 2 : kUnroll;   // columns in flight
-    const int wave = threadIdx.x >> 6;
     const int p = bd.rank;
     const uint8_t* Up = kp.fac + bd.u_off + (int64_t(chunk0) * p + rin) * S;
     CT lacc[RPL][RG];
@@ -411,38 +417,26 @@ __device__ void expand_level(const KParams& kp, const BlockDesc& bd, int chunk0,
     for (int i = 0; i < RPL; ++i)
 #pragma unroll
         for (int rg = 0; rg < RG; ++rg) lacc[i][rg] = CT(0);
-    int j = wave;
-    for (; j + (UN - 1) * kWaves < p; j += UN * kWaves) {
+    // every column of the level, UN loads in flight (the last group guarded)
+    for (int j = 0; j < p; j += UN) {
         CT u[UN][RPL];
 #pragma unroll
         for (int q = 0; q < UN; ++q) {
-            if (act)
-                Codec<F>::template load<RPL, CT>(Up + int64_t(j + q * kWaves) * ld * S, u[q]);
+            if (act && j + q < p)
+                Codec<F>::template load<RPL, CT>(Up + int64_t(j + q) * ld * S, u[q]);
             else
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) u[q][i] = CT(0);
         }
 #pragma unroll
-        for (int q = 0; q < UN; ++q)
+        for (int q = 0; q < UN; ++q) {
+            if (j + q >= p) break;
 #pragma unroll
             for (int rg = 0; rg < RG; ++rg) {
-                const CT tv = CT(ts[rg * p + j + q * kWaves]);
+                const CT tv = CT(ts[rg * p + j + q]);
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) lacc[i][rg] += u[q][i] * tv;
             }
-    }
-    for (; j < p; j += kWaves) {
-        CT u[RPL];
-        if (act)
-            Codec<F>::template load<RPL, CT>(Up + int64_t(j) * ld * S, u);
-        else
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) u[i] = CT(0);
-#pragma unroll
-        for (int rg = 0; rg < RG; ++rg) {
-            const CT tv = CT(ts[rg * p + j]);
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) lacc[i][rg] += u[i] * tv;
         }
     }
 #pragma unroll
@@ -451,20 +445,102 @@ __device__ void expand_level(const KParams& kp, const BlockDesc& bd, int chunk0,
         for (int rg = 0; rg < RG; ++rg) acc[i][rg] += AT(lacc[i][rg]);
 }
 
-template <typename XT, typename AT, int RG, int RPL>
-__device__ void run_expand(const KParams& kp, int tile, const XT* __restrict__ X, int64_t ldx,
-                           XT* __restrict__ Y, int64_t ldy, int nrhs, unsigned char* smem, int* s_off) {
+// Leaf tile of the first launch (wave path): W rows of the tile = D_i X_i,
+// summed over the four waves in fp64 and stored once (padded row space,
+// ld npad).  Lane l owns rows RPL*l.. of the tile; wave w walks columns
+// w, w+4, ... of D_i with kLeafUnroll loads in flight; x_i is staged in LDS.
+template <typename XT, int RG, int RPL>
+__device__ void run_leaf(const KParams& kp, int tile, const XT* __restrict__ X, int64_t ldx, int nrhs,
+                         unsigned char* smem) {
     constexpr int TR = 64 * RPL;                    // rows per tile
     const ETile t = kp.etiles[tile];
     const LeafDesc L = kp.leaves[t.leaf];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int row = t.r0 + RPL * lane;              // padded row within the leaf
+    const bool act = RPL * lane < t.nr;
+    // LDS: x of the leaf [m][RG] | wave sums [kWaves][TR]
+    double* xs = reinterpret_cast<double*>(smem);
+    double* red = xs + int64_t(L.m) * RG;
+    for (int rb = 0; rb < nrhs; rb += RG) {
+        for (int idx = threadIdx.x; idx < L.m * RG; idx += kThreads) {
+            const int c = idx / RG, rg = idx % RG;
+            xs[idx] = (rb + rg < nrhs) ? double(X[L.row0 + c + ldx * (rb + rg)]) : 0.0;
+        }
+        __syncthreads();
+        double dacc[RPL][RG];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i)
+#pragma unroll
+            for (int rg = 0; rg < RG; ++rg) dacc[i][rg] = 0.0;
+        // the tile's chunk of D_i: column-major, ld = t.nr
+        const uint8_t* Dp = reinterpret_cast<const uint8_t*>(kp.leafd + L.d_off + int64_t(t.r0) * L.mp + RPL * lane);
+        const int64_t ldb = int64_t(t.nr) * 8;
+        int c = wave;
+        for (; c + (kLeafUnroll - 1) * kWaves < L.m; c += kLeafUnroll * kWaves) {
+            double d[kLeafUnroll][RPL];
+#pragma unroll
+            for (int q = 0; q < kLeafUnroll; ++q) {
+                if (act)
+                    Codec<F64>::template load<RPL, double>(Dp + int64_t(c + q * kWaves) * ldb, d[q]);
+                else
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) d[q][i] = 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < kLeafUnroll; ++q)
+#pragma unroll
+                for (int rg = 0; rg < RG; ++rg) {
+                    const double xv = xs[(c + q * kWaves) * RG + rg];
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) dacc[i][rg] += d[q][i] * xv;
+                }
+        }
+        for (; c < L.m; c += kWaves) {
+            double d[RPL];
+            if (act)
+                Codec<F64>::template load<RPL, double>(Dp + int64_t(c) * ldb, d);
+            else
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) d[i] = 0.0;
+#pragma unroll
+            for (int rg = 0; rg < RG; ++rg) {
+                const double xv = xs[c * RG + rg];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) dacc[i][rg] += d[i] * xv;
+            }
+        }
+        // sum the waves' partial rows in fp64; store W once
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) red[wave * TR + RPL * lane + i] = dacc[i][rg];
+            __syncthreads();
+            for (int r = threadIdx.x; r < TR; r += kThreads) {
+                double sum = red[r];
+#pragma unroll
+                for (int w = 1; w < kWaves; ++w) sum += red[w * TR + r];
+                if (r < t.nr && rb + rg < nrhs) kp.W[int64_t(L.prow0) + t.r0 + r + kp.npad * (rb + rg)] = sum;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Expansion tile of the second launch (wave path): Y rows of one leaf tile
+// = W + sum_k U_b T_b over the tile's depth ancestor blocks; the waves'
+// partial rows are added in LDS and Y is written once.
+template <typename XT, typename AT, int RG, int RPL>
+__device__ void run_expand(const KParams& kp, int tile, XT* __restrict__ Y, int64_t ldy, int nrhs,
+                           unsigned char* smem, int* s_off) {
+    constexpr int TR = 64 * RPL;                    // rows per tile
+    const ETile t = kp.etiles[tile];
+    const LeafDesc L = kp.leaves[t.leaf];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     const bool act = RPL * lane < t.nr;
     const int depth = kp.depth;
-    // LDS: x of the leaf [m][RG] | T of every level [sum p][RG] | wave sums [kWaves][TR]
-    double* xs = reinterpret_cast<double*>(smem);
-    double* ts = xs + int64_t(L.m) * RG;
+    // LDS: T of every level [sum p][RG] | wave sums [kWaves][TR]
+    double* ts = reinterpret_cast<double*>(smem);
     // level offsets of T in LDS: thread k-1 reads level k's rank, thread 0 adds up
     if (threadIdx.x < depth) {
         const int k = threadIdx.x + 1;
@@ -483,60 +559,11 @@ __device__ void run_expand(const KParams& kp, int tile, const XT* __restrict__ X
     __syncthreads();
     AT* red = reinterpret_cast<AT*>(ts + s_off[depth]);
     for (int rb = 0; rb < nrhs; rb += RG) {
-        for (int idx = threadIdx.x; idx < L.m * RG; idx += kThreads) {
-            const int c = idx / RG, rg = idx % RG;
-            xs[idx] = (rb + rg < nrhs) ? double(X[L.row0 + c + ldx * (rb + rg)]) : 0.0;
-        }
-        __syncthreads();
         AT acc[RPL][RG];
-        {
-            double dacc[RPL][RG];
 #pragma unroll
-            for (int i = 0; i < RPL; ++i)
+        for (int i = 0; i < RPL; ++i)
 #pragma unroll
-                for (int rg = 0; rg < RG; ++rg) dacc[i][rg] = 0.0;
-            // the tile's chunk of D_i: column-major, ld = t.nr
-            const uint8_t* Dp = reinterpret_cast<const uint8_t*>(kp.leafd + L.d_off + int64_t(t.r0) * L.mp + RPL * lane);
-            const int64_t ldb = int64_t(t.nr) * 8;
-            int c = wave;
-            for (; c + (kLeafUnroll - 1) * kWaves < L.m; c += kLeafUnroll * kWaves) {
-                double d[kLeafUnroll][RPL];
-#pragma unroll
-                for (int q = 0; q < kLeafUnroll; ++q) {
-                    if (act)
-                        Codec<F64>::template load<RPL, double>(Dp + int64_t(c + q * kWaves) * ldb, d[q]);
-                    else
-#pragma unroll
-                        for (int i = 0; i < RPL; ++i) d[q][i] = 0.0;
-                }
-#pragma unroll
-                for (int q = 0; q < kLeafUnroll; ++q)
-#pragma unroll
-                    for (int rg = 0; rg < RG; ++rg) {
-                        const double xv = xs[(c + q * kWaves) * RG + rg];
-#pragma unroll
-                        for (int i = 0; i < RPL; ++i) dacc[i][rg] += d[q][i] * xv;
-                    }
-            }
-            for (; c < L.m; c += kWaves) {
-                double d[RPL];
-                if (act)
-                    Codec<F64>::template load<RPL, double>(Dp + int64_t(c) * ldb, d);
-                else
-#pragma unroll
-                    for (int i = 0; i < RPL; ++i) d[i] = 0.0;
-#pragma unroll
-                for (int rg = 0; rg < RG; ++rg) {
-                    const double xv = xs[c * RG + rg];
-#pragma unroll
-                    for (int i = 0; i < RPL; ++i) dacc[i][rg] += d[i] * xv;
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < RPL; ++i)
-#pragma unroll
-                for (int rg = 0; rg < RG; ++rg) acc[i][rg] = AT(dacc[i][rg]);
-        }
+            for (int rg = 0; rg < RG; ++rg) acc[i][rg] = AT(0);
         // T of every level for right-hand sides [rb, rb+RG): one pass of loads
         for (int idx = threadIdx.x; idx < s_off[depth]; idx += kThreads) {
             int k = 1;
@@ -548,7 +575,9 @@ __device__ void run_expand(const KParams& kp, int tile, const XT* __restrict__ X
             ts[idx] = (rb + rg < nrhs) ? kp.T[bd.t_off * nrhs + int64_t(rb + rg) * p + j] : 0.0;
         }
         __syncthreads();
-        for (int k = 1; k <= depth; ++k) {
+        // the waves take whole levels (wave w: levels w+1, w+5, ...), so the
+        // chain of dependent loads per wave is short
+        for (int k = 1 + wave; k <= depth; k += kWaves) {
             const int b = (1 << k) - 2 + (t.leaf >> (depth - k));
             const BlockDesc bd = kp.blocks[b];
             if (bd.rank == 0) continue;
@@ -564,19 +593,20 @@ __device__ void run_expand(const KParams& kp, int tile, const XT* __restrict__ X
                 default: expand_level<E5M2, AT, AT, RG, RPL>(kp, bd, c0, rin, t.nr, act, tk, acc); break;
             }
         }
-        // sum the waves' partial rows; write Y once
+        // sum the waves' partial rows, add the leaf product; write Y once
 #pragma unroll
         for (int rg = 0; rg < RG; ++rg) {
 #pragma unroll
             for (int i = 0; i < RPL; ++i) red[wave * TR + RPL * lane + i] = acc[i][rg];
             __syncthreads();
             for (int r = threadIdx.x; r < TR; r += kThreads) {
-                AT s = red[r];
+                AT sum = red[r];
 #pragma unroll
-                for (int w = 1; w < kWaves; ++w) s += red[w * TR + r];
+                for (int w = 1; w < kWaves; ++w) sum += red[w * TR + r];
                 const int lr = t.r0 + r;
                 if (r < t.nr && lr < L.m && rb + rg < nrhs)
-                    Y[L.row0 + lr + ldy * (rb + rg)] = XT(s);
+                    Y[L.row0 + lr + ldy * (rb + rg)] =
+                        XT(sum + AT(kp.W[int64_t(L.prow0) + lr + kp.npad * (rb + rg)]));
             }
             __syncthreads();
         }
@@ -586,22 +616,34 @@ __device__ void run_expand(const KParams& kp, int tile, const XT* __restrict__ X
 // ---------------------------------------------------------------------------
 // the two launches
 // ---------------------------------------------------------------------------
-template <typename XT, typename AT, int RG>
-__global__ __launch_bounds__(kThreads, HODLR_CONTRACT_MINW) void k_contract(KParams kp, const XT* __restrict__ Xc, int64_t ldc,
-                                                       int nrhs, int stage_cap) {
-    extern __shared__ double smem_d[];
-    __shared__ int s_flag;
-    run_contract<XT, AT, RG>(kp, blockIdx.x, Xc, ldc, nrhs, reinterpret_cast<unsigned char*>(smem_d), &s_flag,
-                             stage_cap);
+// First launch: workgroups [0, ncitems) take contraction items, the rest
+// the leaf tiles (nothing in it waits for anything else in it).
+template <typename XT, typename AT, int RG, int RPL>
+__device__ void run_phase1(const KParams& kp, int w, const XT* __restrict__ Xc, int64_t ldc,
+                           const XT* __restrict__ X, int64_t ldx, int nrhs, int stage_cap, unsigned char* smem,
+                           int* s_flag) {
+    if (w < kp.ncitems)
+        run_contract<XT, AT, RG>(kp, w, Xc, ldc, nrhs, smem, s_flag, stage_cap);
+    else
+        run_leaf<XT, RG, RPL>(kp, w - kp.ncitems, X, ldx, nrhs, smem);
 }
 
 template <typename XT, typename AT, int RG, int RPL>
-__global__ __launch_bounds__(kThreads, HODLR_EXPAND_MINW) void k_expand(KParams kp, const XT* __restrict__ X, int64_t ldx,
-                                                     XT* __restrict__ Y, int64_t ldy, int nrhs) {
+__global__ __launch_bounds__(kThreads, HODLR_CONTRACT_MINW) void k_phase1(KParams kp, const XT* __restrict__ Xc,
+                                                                         int64_t ldc, const XT* __restrict__ X,
+                                                                         int64_t ldx, int nrhs, int stage_cap) {
+    extern __shared__ double smem_d[];
+    __shared__ int s_flag;
+    run_phase1<XT, AT, RG, RPL>(kp, blockIdx.x, Xc, ldc, X, ldx, nrhs, stage_cap,
+                                reinterpret_cast<unsigned char*>(smem_d), &s_flag);
+}
+
+template <typename XT, typename AT, int RG, int RPL>
+__global__ __launch_bounds__(kThreads, HODLR_EXPAND_MINW) void k_expand(KParams kp, XT* __restrict__ Y, int64_t ldy,
+                                                                       int nrhs) {
     extern __shared__ double smem_d[];
     __shared__ int s_off[kMaxDepth + 1];
-    run_expand<XT, AT, RG, RPL>(kp, blockIdx.x, X, ldx, Y, ldy, nrhs, reinterpret_cast<unsigned char*>(smem_d),
-                                s_off);
+    run_expand<XT, AT, RG, RPL>(kp, blockIdx.x, Y, ldy, nrhs, reinterpret_cast<unsigned char*>(smem_d), s_off);
 }
 
 // ---------------------------------------------------------------------------
@@ -647,9 +689,17 @@ int stage_cap(const KParams& kp, int rg) {
     return int(need < kStageMax ? (need > 0 ? need : 1) : kStageMax);
 }
 
-// expansion tile LDS: x of the leaf | T of its levels (doubles) | wave sums
+// expansion tile LDS (wave path): T of its levels (doubles) | wave sums
 size_t lds_expand(const KParams& kp, int rg, size_t acc_bytes) {
-    return (size_t(kp.max_leaf) + size_t(kp.max_rank_path)) * rg * 8 + size_t(kWaves) * kTileRows * acc_bytes;
+    return size_t(kp.max_rank_path) * rg * 8 + size_t(kWaves) * kTileRows * acc_bytes;
+}
+
+// first launch LDS: the larger of a contraction item's staging and a leaf
+// tile's x of the leaf plus wave sums (doubles)
+size_t lds_phase1(const KParams& kp, int rg) {
+    const size_t leaf = (size_t(kp.max_leaf) * rg + size_t(kWaves) * kTileRows) * 8;
+    const size_t stage = size_t(stage_cap(kp, rg)) * 8;
+    return leaf > stage ? leaf : stage;
 }
 
 template <typename XT, typename AT, int RG, int RPL>
@@ -667,16 +717,14 @@ hipError_t launch_typed(const KParams& kp, const void* Xv, int64_t ldx, void* Yv
         Xc = static_cast<const XT*>(kp.xpad);
         ldc = kp.npad;
     }
-    if (kp.ncitems > 0) {
-        const int sc = stage_cap(kp, RG);
-        tm.begin(1);
-        hipLaunchKernelGGL((k_contract<XT, AT, RG>), dim3(kp.ncitems), dim3(kThreads), size_t(sc) * 8, s, kp, Xc,
-                           ldc, nrhs, sc);
-        tm.end(1);
-    }
+    const int sc = stage_cap(kp, RG);
+    tm.begin(1);
+    hipLaunchKernelGGL((k_phase1<XT, AT, RG, RPL>), dim3(kp.ncitems + kp.netiles), dim3(kThreads),
+                       lds_phase1(kp, RG), s, kp, Xc, ldc, X, ldx, nrhs, sc);
+    tm.end(1);
     tm.begin(2);
     hipLaunchKernelGGL((k_expand<XT, AT, RG, RPL>), dim3(kp.netiles), dim3(kThreads), lds_expand(kp, RG, sizeof(AT)),
-                       s, kp, X, ldx, Y, ldy, nrhs);
+                       s, kp, Y, ldy, nrhs);
     tm.end(2);
     return hipGetLastError();
 }
@@ -684,14 +732,15 @@ hipError_t launch_typed(const KParams& kp, const void* Xv, int64_t ldx, void* Yv
 template <typename XT, typename AT>
 hipError_t launch_rg(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs,
                      const Timer& tm) {
-    // the widest right-hand-side group whose LDS fits in 64 KB
-    int rg = nrhs == 1 ? 1 : nrhs == 2 ? 2 : nrhs <= 4 ? 4 : 8;
-    while (rg > 1 && lds_expand(kp, rg, sizeof(AT)) > kMaxLds) rg /= 2;
-    if (lds_expand(kp, rg, sizeof(AT)) > kMaxLds) return hipErrorInvalidConfiguration;
+    // the widest right-hand-side group (at most 4: wider ones spill registers)
+    // whose LDS fits in 64 KB
+    int rg = nrhs == 1 ? 1 : nrhs == 2 ? 2 : 4;
+    auto fits = [&](int g) { return lds_expand(kp, g, sizeof(AT)) <= kMaxLds && lds_phase1(kp, g) <= kMaxLds; };
+    while (rg > 1 && !fits(rg)) rg /= 2;
+    if (!fits(rg)) return hipErrorInvalidConfiguration;
     if (rg == 1) return launch_typed<XT, AT, 1, kRPL>(kp, X, ldx, Y, ldy, nrhs, tm);
     if (rg == 2) return launch_typed<XT, AT, 2, kRPL>(kp, X, ldx, Y, ldy, nrhs, tm);
-    if (rg == 4) return launch_typed<XT, AT, 4, kRPL>(kp, X, ldx, Y, ldy, nrhs, tm);
-    return launch_typed<XT, AT, 8, kRPL>(kp, X, ldx, Y, ldy, nrhs, tm);
+    return launch_typed<XT, AT, 4, kRPL>(kp, X, ldx, Y, ldy, nrhs, tm);
 }
 
 // ---------------------------------------------------------------------------
@@ -707,7 +756,6 @@ hipError_t launch_rg(const KParams& kp, const void* X, int64_t ldx, void* Y, int
 // to agree between A and B, so lane l feeds its own kKL consecutive rows
 // (one vector load) to kKL successive MFMAs: lane group g = l/16 of a 32-row
 // step takes rows 8g..8g+7.
-constexpr int kWideMin = 16;
 constexpr int kKL = 8;                      // consecutive rows per lane per step
 constexpr int kStep = 4 * kKL;              // rows per MFMA step (4 lane groups)
 
@@ -1299,17 +1347,20 @@ __global__ __launch_bounds__(256) void kb_padx(const BatchOp* __restrict__ ops, 
     }
 }
 
-template <typename XT, typename AT, int RG>
-__global__ __launch_bounds__(kThreads, HODLR_CONTRACT_MINW) void kb_contract(const BatchOp* __restrict__ ops,
-                                                                            const WorkItem* __restrict__ w, int nw,
-                                                                            int stage_cap) {
+// wave-path first launch over many operators: idx is a contraction item
+// (y == 0) or a leaf tile (y == 1) of operator op
+template <typename XT, typename AT, int RG, int RPL>
+__global__ __launch_bounds__(kThreads, HODLR_CONTRACT_MINW) void kb_phase1(const BatchOp* __restrict__ ops,
+                                                                          const WorkItem* __restrict__ w, int nw,
+                                                                          int stage_cap) {
     extern __shared__ double smem_d[];
     __shared__ int s_flag;
     for (int i = blockIdx.x; i < nw; i += gridDim.x) {
         const WorkItem wi = w[i];
         const BatchOp& o = ops[wi.op];
-        run_contract<XT, AT, RG>(o.kp, wi.idx, static_cast<const XT*>(o.Xc), o.ldc, o.nrhs,
-                                 reinterpret_cast<unsigned char*>(smem_d), &s_flag, stage_cap);
+        run_phase1<XT, AT, RG, RPL>(o.kp, wi.y ? o.kp.ncitems + wi.idx : wi.idx, static_cast<const XT*>(o.Xc), o.ldc,
+                                    static_cast<const XT*>(o.X), o.ldx, o.nrhs, stage_cap,
+                                    reinterpret_cast<unsigned char*>(smem_d), &s_flag);
         __syncthreads();
     }
 }
@@ -1322,8 +1373,8 @@ __global__ __launch_bounds__(kThreads, HODLR_EXPAND_MINW) void kb_expand(const B
     for (int i = blockIdx.x; i < nw; i += gridDim.x) {
         const WorkItem wi = w[i];
         const BatchOp& o = ops[wi.op];
-        run_expand<XT, AT, RG, RPL>(o.kp, wi.idx, static_cast<const XT*>(o.X), o.ldx, static_cast<XT*>(o.Y), o.ldy,
-                                    o.nrhs, reinterpret_cast<unsigned char*>(smem_d), s_off);
+        run_expand<XT, AT, RG, RPL>(o.kp, wi.idx, static_cast<XT*>(o.Y), o.ldy, o.nrhs,
+                                    reinterpret_cast<unsigned char*>(smem_d), s_off);
         __syncthreads();
     }
 }
@@ -1370,7 +1421,7 @@ hipError_t batch_narrow(const BatchGroup& g, hipStream_t s) {
     if (g.n_padx)
         hipLaunchKernelGGL((kb_padx<XT>), dim3(g.grid[0]), dim3(256), 0, s, g.ops, g.padx, g.n_padx);
     if (g.n_contract)
-        hipLaunchKernelGGL((kb_contract<XT, AT, RG>), dim3(g.grid[1]), dim3(kThreads), size_t(g.lds_contract), s,
+        hipLaunchKernelGGL((kb_phase1<XT, AT, RG, kRPL>), dim3(g.grid[1]), dim3(kThreads), size_t(g.lds_contract), s,
                            g.ops, g.contract, g.n_contract, g.stage_cap);
     if (g.n_expand)
         hipLaunchKernelGGL((kb_expand<XT, AT, RG, kRPL>), dim3(g.grid[3]), dim3(kThreads), size_t(g.lds_expand), s,
@@ -1400,8 +1451,7 @@ hipError_t batch_typed(const BatchGroup& g, hipStream_t s) {
         switch (g.rg) {
             case 1: return batch_narrow<XT, AT, 1>(g, s);
             case 2: return batch_narrow<XT, AT, 2>(g, s);
-            case 4: return batch_narrow<XT, AT, 4>(g, s);
-            default: return batch_narrow<XT, AT, 8>(g, s);
+            default: return batch_narrow<XT, AT, 4>(g, s);
         }
     }
     switch (g.rg) {
@@ -1442,14 +1492,15 @@ int plan_launch(const KParams& kp, const void* X, int64_t ldx, int nrhs, bool xy
     const size_t acc_bytes = acc_double ? 8 : 4;
     const size_t xbytes = xy_double ? 8 : 4;
     if (nrhs < kWideMin) {
-        int rg = nrhs == 1 ? 1 : nrhs == 2 ? 2 : nrhs <= 4 ? 4 : 8;
-        while (rg > 1 && lds_expand(kp, rg, acc_bytes) > kMaxLds) rg /= 2;
-        if (lds_expand(kp, rg, acc_bytes) > kMaxLds) return int(hipErrorInvalidConfiguration);
+        int rg = nrhs == 1 ? 1 : nrhs == 2 ? 2 : 4;
+        auto fits = [&](int g) { return lds_expand(kp, g, acc_bytes) <= kMaxLds && lds_phase1(kp, g) <= kMaxLds; };
+        while (rg > 1 && !fits(rg)) rg /= 2;
+        if (!fits(rg)) return int(hipErrorInvalidConfiguration);
         o.wide = 0;
         o.rg = rg;
         o.padx = kp.padded && kp.ncitems > 0;
         o.stage_cap = stage_cap(kp, rg);
-        o.lds_contract = int64_t(o.stage_cap) * 8;
+        o.lds_contract = int64_t(lds_phase1(kp, rg));
         o.lds_expand = int64_t(lds_expand(kp, rg, acc_bytes));
     } else {
         const int nt = nrhs <= 16 ? 1 : nrhs <= 32 ? 2 : (nrhs <= 64 || xy_double) ? 4 : 8;

@@ -1,6 +1,6 @@
 """GPU parity: the HIP product against the oracle, through the C ABI.
 
-Products with nrhs >= 16 take the matrix-core path (fp64 MFMA leaf GEMMs,
+Products with nrhs >= 8 take the matrix-core path (fp64 MFMA leaf GEMMs,
 fp32/fp64 MFMA low-rank tiles); smaller ones the wave-reduction path.  Both
 are checked here, on the same operators.
 
