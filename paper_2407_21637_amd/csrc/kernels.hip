@@ -980,7 +980,8 @@ __device__ __forceinline__ int round4(int v) { return (v + 3) & ~3; }
 // One level's U_b T_b added to a wave's two 16-row tiles (accumulators in
 // the fp64 row layout).  T_b comes from LDS as ts[j][c]: staged whole
 // before the call (jc == 0; round_up(p, 4) rows), or here, jc rows at a
-// time.  MFMA q of a 32-rank group takes ranks j0 + 4q + (l/16), so groups
+// time.  Within the staged rows the U operands of QG MFMA groups (4 ranks
+// each: MFMA q takes ranks j0 + 4q + (l/16)) are loaded at once; groups
 // past the rank are skipped.
 template <int F, typename CT, int NT>
 __device__ void expand_level_w(const KParams& kp, const BlockDesc& bd, int chunk0, int ld, int c0, int nrhs,
@@ -989,42 +990,46 @@ __device__ void expand_level_w(const KParams& kp, const BlockDesc& bd, int chunk
     constexpr int S = Codec<F>::kBytes;
     constexpr int CW = 16 * NT;
     constexpr int TS = CW + 4;
+    constexpr int QG = (NT <= 2 && sizeof(CT) == 4) ? 2 * kKL : kKL;   // MFMA groups per batch of U loads
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, g = lane >> 4;
     const int p = bd.rank;
     const uint8_t* Up = kp.fac + bd.u_off + int64_t(chunk0) * p * S;
     // fp32 results are steered into the fp64 row layout of the accumulators
     const int r0 = 32 * wave + (sizeof(CT) == 8 ? li : f64_layout_row(li)), r1 = r0 + 16;
-    const int stride = jc ? jc : 4 * kKL;
-    for (int j0 = 0; j0 < p; j0 += stride) {
-        const int left = p - j0 < stride ? p - j0 : stride;
-        const CT* tj = ts + (jc ? 0 : j0 * TS);
+    const int chunk = jc ? jc : p;
+    for (int cr0 = 0; cr0 < p; cr0 += chunk) {
+        const int crows = p - cr0 < chunk ? p - cr0 : chunk;
         if (jc) {
             __syncthreads();                            // previous users of ts are done
-            stage_t<CT, CW>(kp, bd, j0, round4(left), c0, nrhs, ts);
+            stage_t<CT, CW>(kp, bd, cr0, round4(crows), c0, nrhs, ts);
             __syncthreads();
         }
-        const int qn = (left + 3) >> 2;                 // MFMA groups holding some rank < p
-        CT a0[kKL], a1[kKL];
+        const CT* tc = ts + (jc ? 0 : cr0 * TS);
+        for (int j0 = 0; j0 < crows; j0 += 4 * QG) {
+            const int left = crows - j0 < 4 * QG ? crows - j0 : 4 * QG;
+            const int qn = (left + 3) >> 2;             // MFMA groups holding some rank < p
+            CT a0[QG], a1[QG];
 #pragma unroll
-        for (int q = 0; q < kKL; ++q) {
-            const int j = j0 + 4 * q + g;
-            a0[q] = CT(0);
-            a1[q] = CT(0);
-            if (q < qn && j < p) {
-                const uint8_t* col = Up + int64_t(j) * ld * S;
-                if (act0) Codec<F>::template load<1, CT>(col + int64_t(r0) * S, &a0[q]);
-                if (act1) Codec<F>::template load<1, CT>(col + int64_t(r1) * S, &a1[q]);
+            for (int q = 0; q < QG; ++q) {
+                const int jr = j0 + 4 * q + g;          // rank within the staged rows
+                a0[q] = CT(0);
+                a1[q] = CT(0);
+                if (q < qn && jr < crows) {
+                    const uint8_t* col = Up + int64_t(cr0 + jr) * ld * S;
+                    if (act0) Codec<F>::template load<1, CT>(col + int64_t(r0) * S, &a0[q]);
+                    if (act1) Codec<F>::template load<1, CT>(col + int64_t(r1) * S, &a1[q]);
+                }
             }
-        }
 #pragma unroll
-        for (int q = 0; q < kKL; ++q) {
-            if (q >= qn) break;
+            for (int q = 0; q < QG; ++q) {
+                if (q >= qn) break;
 #pragma unroll
-            for (int ct = 0; ct < NT; ++ct) {
-                const CT bv = tj[(4 * q + g) * TS + 16 * ct + li];
-                acc[0][ct] = M::mma(a0[q], bv, acc[0][ct]);
-                acc[1][ct] = M::mma(a1[q], bv, acc[1][ct]);
+                for (int ct = 0; ct < NT; ++ct) {
+                    const CT bv = tc[(j0 + 4 * q + g) * TS + 16 * ct + li];
+                    acc[0][ct] = M::mma(a0[q], bv, acc[0][ct]);
+                    acc[1][ct] = M::mma(a1[q], bv, acc[1][ct]);
+                }
             }
         }
     }
@@ -1263,6 +1268,25 @@ __device__ void run_expand_w(const KParams& kp, int tile, int yg, const XT* __re
     }
 }
 
+// LDS of the matrix-core expansion: the two X steps, then T of all levels
+// when it fits in 64 KB (jc = 0), else jc rows of T at a time, jc the
+// largest multiple of 16 that fits (fp64 rows, the larger case)
+bool wide_lds(const KParams& kp, int cw, size_t xbytes, int* jc, int64_t* lds) {
+    const int64_t xb = 2 * int64_t(cw) * kXLD * int64_t(xbytes);
+    const int64_t all = int64_t(kp.max_tstage) * (cw + 4);
+    if (xb + all <= kMaxLds) {
+        *jc = 0;
+        *lds = xb + all;
+        return true;
+    }
+    const int64_t rowb = int64_t(cw + 4) * 8;
+    const int64_t rows = (kMaxLds - xb) / rowb / 16 * 16;
+    if (rows < 16) return false;
+    *jc = int(rows);
+    *lds = xb + rows * rowb;
+    return true;
+}
+
 template <typename XT, typename AT, int NT>
 __global__ __launch_bounds__(kThreads) void k_expand_w(KParams kp, const XT* __restrict__ Xw, int64_t ldw,
                                                        XT* __restrict__ Y, int64_t ldy, int nrhs, int lds_bytes,
@@ -1290,17 +1314,10 @@ hipError_t launch_wide_nt(const KParams& kp, const XT* Xw, int64_t ldw, XT* Y, i
         tm.end(3);
     }
     // LDS: two X steps, then T of all levels if it fits in 64 KB, else T
-    // in chunks of 32 (or 16) rows
-    const int64_t xb = 2 * int64_t(CW) * kXLD * sizeof(XT);
-    const int64_t all = int64_t(kp.max_tstage) * (CW + 4);
-    const int64_t ch32 = int64_t(32) * (CW + 4) * 8, ch16 = ch32 / 2;
+    // in chunks of as many rows as fit (a multiple of 16)
     int jc = 0;
-    int64_t lds = xb + all;
-    if (lds > kMaxLds) {
-        jc = xb + ch32 <= kMaxLds ? 32 : 16;
-        lds = xb + (jc == 32 ? ch32 : ch16);
-        if (lds > kMaxLds) return hipErrorInvalidConfiguration;
-    }
+    int64_t lds = 0;
+    if (!wide_lds(kp, CW, sizeof(XT), &jc, &lds)) return hipErrorInvalidConfiguration;
     tm.begin(2);
     hipLaunchKernelGGL((k_expand_w<XT, AT, NT>), dim3(kp.netiles, (nrhs + CW - 1) / CW), dim3(kThreads),
                        size_t(lds), s, kp, Xw, ldw, Y, ldy, nrhs, int(lds), jc);
@@ -1342,7 +1359,7 @@ __global__ __launch_bounds__(256) void kb_padx(const BatchOp* __restrict__ ops, 
                                                int nw) {
     for (int i = blockIdx.x; i < nw; i += gridDim.x) {
         const WorkItem wi = w[i];
-        const BatchOp& o = ops[wi.op];
+        const BatchOp o = ops[wi.op];                  // uniform: the step's operator
         padx_leaf<XT>(o.kp, wi.idx, static_cast<const XT*>(o.X), o.ldx, o.nrhs);
     }
 }
@@ -1357,7 +1374,7 @@ __global__ __launch_bounds__(kThreads, HODLR_CONTRACT_MINW) void kb_phase1(const
     __shared__ int s_flag;
     for (int i = blockIdx.x; i < nw; i += gridDim.x) {
         const WorkItem wi = w[i];
-        const BatchOp& o = ops[wi.op];
+        const BatchOp o = ops[wi.op];                  // uniform: the step's operator
         run_phase1<XT, AT, RG, RPL>(o.kp, wi.y ? o.kp.ncitems + wi.idx : wi.idx, static_cast<const XT*>(o.Xc), o.ldc,
                                     static_cast<const XT*>(o.X), o.ldx, o.nrhs, stage_cap,
                                     reinterpret_cast<unsigned char*>(smem_d), &s_flag);
@@ -1372,7 +1389,7 @@ __global__ __launch_bounds__(kThreads, HODLR_EXPAND_MINW) void kb_expand(const B
     __shared__ int s_off[kMaxDepth + 1];
     for (int i = blockIdx.x; i < nw; i += gridDim.x) {
         const WorkItem wi = w[i];
-        const BatchOp& o = ops[wi.op];
+        const BatchOp o = ops[wi.op];                  // uniform: the step's operator
         run_expand<XT, AT, RG, RPL>(o.kp, wi.idx, static_cast<XT*>(o.Y), o.ldy, o.nrhs,
                                     reinterpret_cast<unsigned char*>(smem_d), s_off);
         __syncthreads();
@@ -1385,7 +1402,7 @@ __global__ __launch_bounds__(kThreads) void kb_contract_w(const BatchOp* __restr
     extern __shared__ double smem_d[];
     for (int i = blockIdx.x; i < nw; i += gridDim.x) {
         const WorkItem wi = w[i];
-        const BatchOp& o = ops[wi.op];
+        const BatchOp o = ops[wi.op];                  // uniform: the step's operator
         run_contract_w<XT, AT, NT>(o.kp, wi.idx, wi.y, static_cast<const XT*>(o.Xc), o.ldc, o.nrhs, smem_d);
         __syncthreads();
     }
@@ -1396,7 +1413,7 @@ __global__ __launch_bounds__(256) void kb_reduce_w(const BatchOp* __restrict__ o
                                                    int nw) {
     for (int i = blockIdx.x; i < nw; i += gridDim.x) {
         const WorkItem wi = w[i];
-        const BatchOp& o = ops[wi.op];
+        const BatchOp o = ops[wi.op];                  // uniform: the step's operator
         run_reduce_w<AT>(o.kp, wi.idx, wi.y, o.nrhs);
     }
 }
@@ -1409,7 +1426,7 @@ __global__ __launch_bounds__(kThreads) void kb_expand_w(const BatchOp* __restric
     __shared__ int s_off[kMaxDepth + 2];
     for (int i = blockIdx.x; i < nw; i += gridDim.x) {
         const WorkItem wi = w[i];
-        const BatchOp& o = ops[wi.op];
+        const BatchOp o = ops[wi.op];                  // uniform: the step's operator
         run_expand_w<XT, AT, NT>(o.kp, wi.idx, wi.y, static_cast<const XT*>(o.Xc), o.ldc, static_cast<XT*>(o.Y),
                                  o.ldy, o.nrhs, lds_bytes, jc, smem_d, s_off);
         __syncthreads();
@@ -1512,16 +1529,11 @@ int plan_launch(const KParams& kp, const void* X, int64_t ldx, int nrhs, bool xy
         o.ntc = ntc;
         o.padx = kp.padded || !aligned;
         o.lds_contract = int64_t(kWaves) * ntc * 256 * 8;
-        const int64_t xb = 2 * int64_t(cw) * kXLD * int64_t(xbytes);
-        const int64_t all = int64_t(kp.max_tstage) * (cw + 4);
-        const int64_t ch32 = int64_t(32) * (cw + 4) * 8, ch16 = ch32 / 2;
-        o.jc = 0;
-        o.lds_expand = xb + all;
-        if (o.lds_expand > kMaxLds) {
-            o.jc = xb + ch32 <= kMaxLds ? 32 : 16;
-            o.lds_expand = xb + (o.jc == 32 ? ch32 : ch16);
-            if (o.lds_expand > kMaxLds) return int(hipErrorInvalidConfiguration);
-        }
+        int jc = 0;
+        int64_t lds = 0;
+        if (!wide_lds(kp, cw, xbytes, &jc, &lds)) return int(hipErrorInvalidConfiguration);
+        o.jc = jc;
+        o.lds_expand = lds;
         o.gy_contract = (nrhs + 16 * ntc - 1) / (16 * ntc);
         o.gy_expand = (nrhs + cw - 1) / cw;
     }

@@ -91,6 +91,38 @@ def test_c2_small_adaptive(nrhs):
     _run(case, h, a.fmt, nrhs, "fp32", "fp32", "c2_s")
 
 
+def test_c3_recipe_small_e4m3_matrix_cores():
+    """The low-accuracy recipe (log kernel, eps 1e-3, {fp16, bf16, e4m3}) at
+    n = 8192: the adaptive rule picks e4m3; 128 right-hand sides take the
+    128-column matrix-core tiles."""
+    case = Case("c3_s")
+    h = case.library_op()
+    h.assign_precision(case.eps, case.cfg.allowed, case.norms2)
+    a = case.oracle_assign(case.cfg.allowed)
+    assert [lv[0] for lv in h.levels()] == a.fmt
+    for nrhs in (1, 128):
+        _run(case, h, a.fmt, nrhs, "fp32", h.info()["acc_dtype"], "c3_s")
+
+
+def test_c5_recipe_small_fp64():
+    """The high-accuracy recipe (clustered 1/(r+1e-5) + n I, eps 1e-10,
+    {fp32, fp16}) at n = 8192: fp64 X and Y, fp64 accumulation, 1 and 16
+    right-hand sides; Thm 3.5 against the dense matrix."""
+    case = Case("c5_s")
+    h = case.library_op()
+    h.assign_precision(case.eps, case.cfg.allowed, case.norms2)
+    a = case.oracle_assign(case.cfg.allowed)
+    assert [lv[0] for lv in h.levels()] == a.fmt
+    assert h.info()["acc_dtype"] == "fp64"
+    A = case.cfg.kernel.dense(case.P)
+    nA = np.sqrt(case.op.norm2_all)
+    for nrhs in (1, 16):
+        X, yg, _, _ = _run(case, h, a.fmt, nrhs, "fp64", "fp64", "c5_s")
+        for j in range(nrhs):
+            eta = np.linalg.norm(yg[:, j] - A @ X[:, j]) / (nA * np.linalg.norm(X[:, j]))
+            assert eta <= BD.matvec_backward_bound(case.depth, case.eps)
+
+
 @pytest.mark.parametrize("fmt", ["fp64", "fp32", "bf16", "fp16", "e4m3", "e5m2"])
 def test_forced_format_every_level(fmt):
     """Alg. "Mixed-precision HODLR Format" with one format at every level."""
