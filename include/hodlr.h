@@ -70,6 +70,7 @@ typedef enum {
 #define HODLR_NO_COLUMN_SCALE 0x1u  /* store fp16/fp8 without per-column 2^e scales */
 #define HODLR_ACC_FP32        0x2u  /* force fp32 accumulation of Y */
 #define HODLR_ACC_FP64        0x4u  /* force fp64 accumulation of Y */
+#define HODLR_PER_BLOCK       0x8u  /* hodlr_assign_precision: one format per block (see there) */
 
 /* One off-diagonal block U V^T: U is r_b x rank (orthonormal columns,
  * eq. (3.1)), V is c_b x rank, both fp64 column-major on the host. */
@@ -150,7 +151,14 @@ hodlr_status hodlr_create(hodlr_op* out, int64_t n, int32_t depth, const int64_t
  * forces it.  The factors are then quantised (round to nearest even, once,
  * from fp64; fp16/fp8 columns scaled by 2^e_j, e_j the largest integer with
  * max_i |F_ij| 2^e_j <= the format's largest finite value) and repacked.
- * E_RANGE if HODLR_NO_COLUMN_SCALE is set and a value overflows. */
+ * E_RANGE if HODLR_NO_COLUMN_SCALE is set and a value overflows.
+ * HODLR_PER_BLOCK: each block b of level k gets its own format, the same
+ * rule with its own norm, xi_b = sqrt(||A_b||_F^2 / nrmAll) in place of
+ * xi_k (never finer than the level's format; the global bound (3.5) still
+ * holds, as the proof of Thm. 3.1 bounds every block separately).
+ * hodlr_get_level keeps reporting the level rule; hodlr_get_block gives
+ * each block's format.  hodlr_set_level_precisions returns to one format
+ * per level. */
 hodlr_status hodlr_assign_precision(hodlr_op op, double eps, const int32_t* allowed,
                                     int32_t n_allowed, const double* norms2, uint32_t flags);
 

@@ -24,6 +24,14 @@ stored in u_k.  Readings where the paper is silent:
 
 ``norms_from_factors`` gives the alternative reading in which xi is taken
 from the stored factors (the H~ of Thm. 3.1) instead of the original blocks.
+
+``assign_blocks`` is the per-block variant (not in the paper's algorithm):
+the same rule with each block's own norm in place of the level maximum,
+xi_b = ||H_b||_F / ||H||_F and u'_b = eps / (2^(k/2) xi_b).  Since
+xi_b <= xi_k, every block gets a format at least as coarse as its level's.
+The proof of Thm. 3.1 bounds the error of each block separately by about
+2 u_b ||H_b||_F <= 2 eps ||H||_F / 2^(k/2) and adds the squares over the
+2^k blocks of each level, so the global bound (3.5) holds unchanged.
 """
 from __future__ import annotations
 
@@ -52,25 +60,46 @@ def level_max_norm2(norm2_blocks, levels) -> list:
     return out
 
 
+def _candidates(allowed, working):
+    return sorted({F.fmt(working).name, *[F.fmt(a).name for a in allowed]},
+                  key=lambda nm: F.FORMATS[nm].u)
+
+
+def _choose(nrm: float, norm2_all: float, k: int, eps: float, cands):
+    """(xi, u', format, insufficient) for squared norm nrm at level k."""
+    xi = math.sqrt(nrm / norm2_all) if norm2_all > 0 else 0.0
+    if xi == 0.0:
+        up = math.inf
+    else:
+        up = eps / (math.sqrt(float(2 ** k)) * xi)
+    ok = [c for c in cands if F.FORMATS[c].u <= up]
+    if ok:
+        return xi, up, max(ok, key=lambda nm: F.FORMATS[nm].u), False
+    return xi, up, "fp64", True
+
+
 def assign(norm2_all: float, nrm_levels, eps: float, allowed,
            working: str = "fp64") -> Assignment:
     """Alg. "Adaptive-precision HODLR Format", the per-level precision choice."""
-    cands = sorted({F.fmt(working).name, *[F.fmt(a).name for a in allowed]},
-                   key=lambda nm: F.FORMATS[nm].u)
+    cands = _candidates(allowed, working)
     xis, ups, fmts, bad = [], [], [], []
     for k, nrm in enumerate(nrm_levels, start=1):
-        xi = math.sqrt(nrm / norm2_all) if norm2_all > 0 else 0.0
-        if xi == 0.0:
-            up = math.inf
-        else:
-            up = eps / (math.sqrt(float(2 ** k)) * xi)
-        ok = [c for c in cands if F.FORMATS[c].u <= up]
-        if ok:
-            choice = max(ok, key=lambda nm: F.FORMATS[nm].u)
-            insufficient = False
-        else:
-            choice = "fp64"
-            insufficient = True
+        xi, up, choice, insufficient = _choose(nrm, norm2_all, k, eps, cands)
+        xis.append(xi)
+        ups.append(up)
+        fmts.append(choice)
+        bad.append(insufficient)
+    return Assignment(xis, ups, fmts, bad)
+
+
+def assign_blocks(norm2_all: float, norm2_blocks, levels, eps: float, allowed,
+                  working: str = "fp64") -> Assignment:
+    """Per-block variant (module docstring): one entry per block, in the
+    order of ``norm2_blocks`` / ``levels``."""
+    cands = _candidates(allowed, working)
+    xis, ups, fmts, bad = [], [], [], []
+    for nrm, k in zip(norm2_blocks, levels):
+        xi, up, choice, insufficient = _choose(float(nrm), norm2_all, int(k), eps, cands)
         xis.append(xi)
         ups.append(up)
         fmts.append(choice)

@@ -76,3 +76,24 @@ def store(h, level_fmt, scale_columns: bool = True) -> StoredHodlr:
         QU.append(quantize(U, f, scale_columns))
         QV.append(quantize(V, f, scale_columns))
     return StoredHodlr(h.n, h.depth, h.blocks, h.leaves, list(level_fmt), QU, QV)
+
+
+def store_blocks(h, block_fmt, scale_columns: bool = True) -> StoredHodlr:
+    """Quantise every block's generators in its own format (the per-block
+    variant of ``oracle.assign.assign_blocks``); ``level_fmt`` is left empty."""
+    QU, QV = [], []
+    for U, V, f in zip(h.U, h.V, block_fmt):
+        QU.append(quantize(U, f, scale_columns))
+        QV.append(quantize(V, f, scale_columns))
+    return StoredHodlr(h.n, h.depth, h.blocks, h.leaves, [], QU, QV)
+
+
+def storage_bits(stored: StoredHodlr) -> int:
+    """Bits of the stored generators: codes plus 8 per scaled column."""
+    bits = 0
+    for q in list(stored.QU) + list(stored.QV):
+        f = F.fmt(q.fmt)
+        bits += q.codes.size * 8 * f.nbytes
+        if f.name in F.SCALED:
+            bits += 8 * q.codes.shape[1]
+    return bits

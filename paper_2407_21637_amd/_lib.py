@@ -22,6 +22,7 @@ CODE_NP = {0: np.uint64, 1: np.uint32, 2: np.uint16, 3: np.uint16, 4: np.uint8, 
 NO_COLUMN_SCALE = 0x1
 ACC_FP32 = 0x2
 ACC_FP64 = 0x4
+PER_BLOCK = 0x8
 
 STATUS = {0: "HODLR_OK", 1: "HODLR_E_ARG", 2: "HODLR_E_STATE", 3: "HODLR_E_NOMEM",
           4: "HODLR_E_DEVICE", 5: "HODLR_E_RANGE", 6: "HODLR_E_UNSUPPORTED"}

@@ -242,6 +242,7 @@ struct hodlr_op_s {
 
     // assignment
     std::vector<int32_t> level_fmt;            // per level k-1
+    std::vector<int32_t> block_fmt;            // per block (HODLR_PER_BLOCK); empty: the level's
     std::vector<double> xi, uprime;
     std::vector<int32_t> insufficient;
     double eps = 0.0;
@@ -471,7 +472,7 @@ hodlr_status pack(hodlr_op_s* op) {
         const int k = hb.level;
         const int64_t j = b - ((int64_t(1) << k) - 2);
         BlockDesc& d = op->bdesc[b];
-        const int f = op->level_fmt[k - 1];
+        const int f = op->block_fmt.empty() ? op->level_fmt[k - 1] : op->block_fmt[b];
         const int p = op->rank[b];
         int64_t up0, upr, vp0, vpr;
         node_padded(op, k, j, &up0, &upr);
@@ -798,14 +799,15 @@ hodlr_status hodlr_assign_precision(hodlr_op op, double eps, const int32_t* allo
     if ((flags & HODLR_ACC_FP32) && (flags & HODLR_ACC_FP64))
         return fail(HODLR_E_ARG, "HODLR_ACC_FP32 and HODLR_ACC_FP64 both set");
     const int depth = op->depth;
-    // nrmAll and per-level maxima of ||H_b||_F^2
+    // nrmAll, ||H_b||_F^2 and their per-level maxima
     double all = 0.0;
-    std::vector<double> lvl(depth, 0.0);
+    std::vector<double> lvl(depth, 0.0), bn2(op->nb, 0.0);
     if (norms2) {
         all = norms2[0];
         for (int b = 0; b < op->nb; ++b) {
             const double v = norms2[1 + b];
             if (!(v >= 0.0)) return fail(HODLR_E_ARG, "norms2[%d] is negative or NaN", 1 + b);
+            bn2[b] = v;
             lvl[op->blocks[b].level - 1] = std::max(lvl[op->blocks[b].level - 1], v);
         }
         if (!(all >= 0.0)) return fail(HODLR_E_ARG, "norms2[0] is negative or NaN");
@@ -829,34 +831,52 @@ hodlr_status hodlr_assign_precision(hodlr_op op, double eps, const int32_t* allo
             for (double v : op->D[i]) all += v * v;
         for (int b = 0; b < op->nb; ++b) {
             all += nb2[b];
+            bn2[b] = nb2[b];
             lvl[op->blocks[b].level - 1] = std::max(lvl[op->blocks[b].level - 1], nb2[b]);
         }
     }
     // candidates: fp64 (the working precision) and the allowed set
     std::vector<int> cand = {F64};
     for (int i = 0; i < n_allowed; ++i) cand.push_back(allowed[i]);
-    std::vector<int32_t> fmt(depth), bad(depth);
-    std::vector<double> xi(depth), up(depth);
-    for (int k = 1; k <= depth; ++k) {
-        const double x = all > 0.0 ? std::sqrt(lvl[k - 1] / all) : 0.0;
+    // the rule for squared norm v at level k: (xi, u', format or -1)
+    auto choose = [&](double v, int k, double* x_out, double* u_out) {
+        const double x = all > 0.0 ? std::sqrt(v / all) : 0.0;
         const double u1 = (x == 0.0) ? INFINITY : eps / (std::sqrt(std::ldexp(1.0, k)) * x);
         int best = -1;
         for (int f : cand)
             if (unit_roundoff(f) <= u1 && (best < 0 || unit_roundoff(f) > unit_roundoff(best))) best = f;
-        xi[k - 1] = x;
-        up[k - 1] = u1;
+        *x_out = x;
+        *u_out = u1;
+        return best;
+    };
+    std::vector<int32_t> fmt(depth), bad(depth);
+    std::vector<double> xi(depth), up(depth);
+    for (int k = 1; k <= depth; ++k) {
+        const int best = choose(lvl[k - 1], k, &xi[k - 1], &up[k - 1]);
         fmt[k - 1] = best < 0 ? F64 : best;
         bad[k - 1] = best < 0 ? 1 : 0;
     }
+    std::vector<int32_t> bfmt;
+    if (flags & HODLR_PER_BLOCK) {
+        bfmt.assign(op->nb, F64);
+        for (int b = 0; b < op->nb; ++b) {
+            double x, u1;
+            const int best = choose(bn2[b], op->blocks[b].level, &x, &u1);
+            bfmt[b] = best < 0 ? F64 : best;
+        }
+    }
     const auto old_fmt = op->level_fmt;
+    const auto old_bfmt = op->block_fmt;
     const bool old_acc = op->acc_double, old_scale = op->scale_cols;
     op->level_fmt = fmt;
+    op->block_fmt = bfmt;
     op->scale_cols = !(flags & HODLR_NO_COLUMN_SCALE);
     op->acc_double = (flags & HODLR_ACC_FP64) ? true : (flags & HODLR_ACC_FP32) ? false : (eps < 1e-7);
     hodlr_status r = pack(op);
     if (r != HODLR_OK) {
         std::string m = g_last_error;
         op->level_fmt = old_fmt;
+        op->block_fmt = old_bfmt;
         op->acc_double = old_acc;
         op->scale_cols = old_scale;
         (void)pack(op);
@@ -880,14 +900,17 @@ hodlr_status hodlr_set_level_precisions(hodlr_op op, const int32_t* per_level, u
         all64 = all64 && per_level[k] == F64;
     }
     const auto old_fmt = op->level_fmt;
+    const auto old_bfmt = op->block_fmt;
     const bool old_acc = op->acc_double, old_scale = op->scale_cols;
     op->level_fmt.assign(per_level, per_level + op->depth);
+    op->block_fmt.clear();
     op->scale_cols = !(flags & HODLR_NO_COLUMN_SCALE);
     op->acc_double = (flags & HODLR_ACC_FP64) ? true : (flags & HODLR_ACC_FP32) ? false : all64;
     hodlr_status r = pack(op);
     if (r != HODLR_OK) {
         std::string m = g_last_error;
         op->level_fmt = old_fmt;
+        op->block_fmt = old_bfmt;
         op->acc_double = old_acc;
         op->scale_cols = old_scale;
         (void)pack(op);
@@ -943,7 +966,7 @@ hodlr_status hodlr_get_block(hodlr_op op, int32_t block, hodlr_block_info* info)
     info->nrows = hb.nrows;
     info->col0 = hb.col0;
     info->ncols = hb.ncols;
-    info->dtype = op->level_fmt[hb.level - 1];
+    info->dtype = op->block_fmt.empty() ? op->level_fmt[hb.level - 1] : op->block_fmt[block];
     info->scaled = (op->scale_cols && scaled_format(info->dtype)) ? 1 : 0;
     return ok();
 }

@@ -123,6 +123,33 @@ def test_c5_recipe_small_fp64():
             assert eta <= BD.matvec_backward_bound(case.depth, case.eps)
 
 
+@pytest.mark.parametrize("nrhs", [1, 3, 24])
+def test_per_block_formats(nrhs):
+    """Per-block precision (HODLR_PER_BLOCK): formats differ inside a level;
+    both product paths against the oracle's per-block stored operator."""
+    from oracle import assign as AS
+    from oracle import matvec as MV
+    # clustered points: block norms vary inside a level, so do the formats
+    case = Case("c5_s", n=4096, depth=4, eps=1e-4)
+    allowed = ("e4m3", "e5m2", "fp16", "bf16", "fp32")
+    h = case.library_op()
+    h.assign_precision(case.eps, allowed, case.norms2, H.PER_BLOCK)
+    levels = [b.level for b in case.blocks]
+    a = AS.assign_blocks(case.op.norm2_all, case.op.norm2_blocks, levels, case.eps, allowed)
+    assert [h.block(b)["dtype"] for b in range(h.nblocks)] == a.fmt
+    assert any(len({f for f, k in zip(a.fmt, levels) if k == kk}) > 1 for kk in range(1, case.depth + 1))
+    assert h.info()["acc_dtype"] == "fp32"
+    U = [Q.quantize(u, f).values for u, f in zip(case.op.U, a.fmt)]
+    V = [Q.quantize(v, f).values for v, f in zip(case.op.V, a.fmt)]
+    X = case.cfg.X(nrhs)[: case.n]
+    y = MV.matvec(case.n, case.blocks, case.leaves_b, case.op.leaves, U, V, X)
+    z = MV.matvec_abs(case.n, case.blocks, case.leaves_b, case.op.leaves, U, V, X)
+    _say(f"[parity] per-block n={case.n} nrhs={nrhs} formats {sorted(set(a.fmt))}")
+    yg = _gpu_product(h, X, "fp64")
+    st = check(yg, y, z, case.chain(), "fp32", "fp64", "per-block")
+    _say(f"    ok {st}")
+
+
 @pytest.mark.parametrize("fmt", ["fp64", "fp32", "bf16", "fp16", "e4m3", "e5m2"])
 def test_forced_format_every_level(fmt):
     """Alg. "Mixed-precision HODLR Format" with one format at every level."""

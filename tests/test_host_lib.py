@@ -84,6 +84,31 @@ def test_assign_matches_oracle_with_given_norms():
             assert h.info()["acc_dtype"] == ("fp64" if eps < 1e-7 else "fp32")
 
 
+def test_per_block_assign_matches_oracle_and_codes_bit_exact():
+    c, depth, op, h = _host_op("c2_s")
+    norms = np.concatenate([[op.norm2_all], op.norm2_blocks])
+    blks = T.blocks(c.n, depth)
+    levels = [b.level for b in blks]
+    allowed = ("e4m3", "e5m2", "fp16", "bf16", "fp32")
+    for eps in (1e-2, 1e-4, 1e-6):
+        h.assign_precision(eps, allowed, norms, H.PER_BLOCK)
+        a = AS.assign_blocks(op.norm2_all, op.norm2_blocks, levels, eps, allowed)
+        got = [h.block(b)["dtype"] for b in range(h.nblocks)]
+        assert got == a.fmt
+        # the level report is still the level rule
+        lv = AS.assign(op.norm2_all, AS.level_max_norm2(op.norm2_blocks, levels), eps, allowed)
+        assert [g[0] for g in h.levels()] == lv.fmt
+        for b in (0, 1, h.nblocks // 2, h.nblocks - 1):
+            uc, ue, vc, ve = h.export_block(b)
+            qu = Q.quantize(op.U[b], a.fmt[b])
+            qv = Q.quantize(op.V[b], a.fmt[b])
+            assert np.array_equal(uc, qu.codes) and np.array_equal(ue, qu.exps)
+            assert np.array_equal(vc, qv.codes) and np.array_equal(ve, qv.exps)
+    # back to one format per level
+    h.set_level_precisions(["fp32"] * depth)
+    assert {h.block(b)["dtype"] for b in range(h.nblocks)} == {"fp32"}
+
+
 def test_assign_from_factors_matches_oracle_reading():
     c, depth, op, h = _host_op("c2_s")
     tot, nb = AS.norms_from_factors(op.leaves, op.U, op.V)

@@ -78,3 +78,31 @@ def test_norms_from_factors_match_dense():
     assert nb[0] == pytest.approx(np.sum((U[0] @ V[0].T) ** 2), rel=1e-13)
     assert nb[1] == 0.0
     assert tot == pytest.approx(np.sum(D[0] ** 2) + nb.sum(), rel=1e-14)
+
+
+def test_per_block_hand_worked():
+    """Per-block variant: each block's own xi in eq. (3.3)."""
+    levels = [1, 1, 2, 2, 2, 2]
+    nrm = [0.01, 1e-6, 0.0025, 0.0025, 1e-8, 0.0]
+    a = A.assign_blocks(1.0, nrm, levels, 1e-4, PAPER_SET + ("e4m3",))
+    # block 0 is its level's maximum: fp16 as in test_hand_worked_levels
+    # block 1: u' = 1e-4 / (sqrt2 * 1e-3) = 7.07e-2 -> e4m3 (6.25e-2); e5m2 (0.125) too big
+    # blocks 2, 3: level 2's maximum -> fp16; block 4: u' = 1e-4 / (2 * 1e-4) = 0.5 -> e5m2
+    # block 5: xi = 0 -> coarsest candidate (e5m2)
+    assert a.fmt == ["fp16", "e4m3", "fp16", "fp16", "e5m2", "e5m2"]
+    assert a.u_prime[1] == pytest.approx(7.0710678e-2, rel=1e-7)
+    assert math.isinf(a.u_prime[5])
+
+
+def test_per_block_never_finer_than_its_level():
+    rng = np.random.default_rng(5)
+    levels = [k for k in range(1, 6) for _ in range(2 ** k)]
+    for eps in (1e-2, 1e-5, 1e-9):
+        nrm = rng.uniform(0, 1, len(levels)) ** 6
+        tot = float(nrm.sum() * 3)
+        lvl = A.assign(tot, A.level_max_norm2(nrm, levels), eps, PAPER_SET)
+        blk = A.assign_blocks(tot, nrm, levels, eps, PAPER_SET)
+        for f, k, v in zip(blk.fmt, levels, nrm):
+            assert F.FORMATS[f].u >= F.FORMATS[lvl.fmt[k - 1]].u
+            if v == max(x for x, kk in zip(nrm, levels) if kk == k):
+                assert f == lvl.fmt[k - 1]

@@ -121,6 +121,37 @@ def test_paper_bounds_on_paper_kernels(cfg, eps):
         assert eta <= BD.matvec_backward_bound(c.depth, eps)
 
 
+@pytest.mark.parametrize("cfg", ["mat1", "mat2", "mat3", "mat4"])
+def test_per_block_variant_keeps_paper_bounds(cfg):
+    """Per-block formats (``assign_blocks``): eq. (3.4) per block with the
+    block's own u_b, eq. (3.5) globally and Thm 3.5 still hold, and the
+    stored generators never take more bits than with one format per level."""
+    c = CF.get(cfg)
+    A = c.kernel.dense(c.points())
+    nA = None
+    for eps in (1e-2, 1e-5):
+        h = C.construct(A, c.depth, eps)
+        nA = np.sqrt(h.norm2_all)
+        levels = [b.level for b in h.blocks]
+        blk = AS.assign_blocks(h.norm2_all, h.norm2_blocks, levels, eps, c.allowed)
+        lvl = AS.assign(h.norm2_all, AS.level_max_norm2(h.norm2_blocks, levels), eps, c.allowed)
+        s = Q.store_blocks(h, blk.fmt)
+        assert np.linalg.norm(A - _dense(s)) <= BD.global_bound_adaptive(c.depth, eps) * nA
+        for b, U, V, QU, QV, f in zip(h.blocks, h.U, h.V, s.QU, s.QV, blk.fmt):
+            Bt = U @ V.T
+            Bh = QU.values @ QV.values.T
+            assert np.linalg.norm(Bt - Bh) <= BD.block_quant_bound(U.shape[1], F.FORMATS[f].u) * \
+                np.linalg.norm(Bt) + 1e-300
+            B = A[b.row0:b.row0 + b.nrows, b.col0:b.col0 + b.ncols]
+            assert np.linalg.norm(B - Bh) <= BD.block_bound_adaptive(b.level, eps) * nA
+        X = c.X(2)
+        Y = _mv(s, X)
+        for j in range(X.shape[1]):
+            eta = np.linalg.norm(Y[:, j] - A @ X[:, j]) / (nA * np.linalg.norm(X[:, j]))
+            assert eta <= BD.matvec_backward_bound(c.depth, eps)
+        assert Q.storage_bits(s) <= Q.storage_bits(Q.store(h, lvl.fmt))
+
+
 def test_eq_3_2_bound_for_forced_precisions():
     """Eq. (3.2) holds for any per-level precisions (Alg. "Mixed-precision
     HODLR Format"), here every level forced to bf16."""
