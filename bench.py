@@ -76,7 +76,7 @@ def build_operator(cfg, H):
     blocks = [(int(r0), int(nr), int(c0), int(nc)) for _, r0, nr, c0, nc in desc]
     P = cfg.points()
     t = time.time()
-    op = compress(cfg.kernel, P, blocks, leaves, cfg.eps, cfg.rule)
+    op = compress(cfg.kernel, P, blocks, leaves, cfg.eps, cfg.rule, method=cfg.extra.get("compress", "random"))
     log(f"[bench] compressed {cfg.name}: n={cfg.n} depth={cfg.depth} in {time.time() - t:.1f}s")
     return P, blocks, leaves, op
 

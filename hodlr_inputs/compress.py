@@ -9,13 +9,23 @@ truncated so that the discarded part meets the rule:
 * ``"spec_global"``: keep singular values > eps * ||A||_2 (``norm_a_2``).
 
 Small blocks use a dense SVD.  Large blocks (more than ``dense_limit``
-entries) use a randomised range finder evaluated tile by tile: Y = B Omega,
-Q = orth(Y), M = Q^T B, SVD of M.  The residual ||B - Q M||_F is known
-(either exactly from a third pass, or as ||B||_F^2 - ||M||_F^2 when eps is
-large enough for that difference to be accurate), so the rank chosen meets
-the rule exactly for the factors produced; the sketch grows until it does.
-||B||_F^2 of every block and of every leaf is accumulated on the way, so
-||A||_F^2 = sum of them is exact.
+entries) use, with ``method="random"``, a randomised range finder evaluated
+tile by tile: Y = B Omega, Q = orth(Y), M = Q^T B, SVD of M.  The residual
+||B - Q M||_F is known (either exactly from a third pass, or as
+||B||_F^2 - ||M||_F^2 when eps is large enough for that difference to be
+accurate), so the rank chosen meets the rule exactly for the factors
+produced; the sketch grows until it does.  ||B||_F^2 of every block and of
+every leaf is accumulated on the way, so ||A||_F^2 = sum of them is exact.
+
+``method="aca"`` is for operators too large to evaluate every entry (the
+2^20-point workload): adaptive cross approximation with partial pivoting
+(Bebendorf, Numer. Math. 86 (2000)) touches O((r + c) k) entries of a block
+for k crosses, stopping when the last cross is below eps/16 of the
+approximant's norm; the crosses are recompressed (QR of both sides, SVD of
+the small core) and truncated by the same rule, with ||B||_F^2 taken as the
+approximant's plus the residual's, the residual estimated from 16 sampled
+rows (a statistical certificate, kept in ``Compressed.certificate``; exact
+norms are not available at that size).
 
 The result is the input of the library's ``hodlr_create`` (and of the
 oracle's tests): fp64 leaves, fp64 U_b, V_b, and the squared norms.
@@ -42,7 +52,8 @@ class Compressed:
     V: list                          # fp64 c_b x p_b
     norm2_all: float
     norm2_blocks: np.ndarray
-    sketch: list = field(default_factory=list)   # per block: 0 dense, else sketch width
+    sketch: list = field(default_factory=list)   # per block: 0 dense, else sketch width / crosses
+    certificate: list = field(default_factory=list)   # per block (aca): sampled residual / ||B||_F
 
     @property
     def ranks(self):
@@ -137,8 +148,70 @@ def _random_block(kernel, P, b, eps, rule, norm_a_2, pool, rng, s0):
         s = min(min(nr, nc), 2 * s)
 
 
+def _aca_block(kernel, P, b, eps, rule, norm_a_2, rng, sample_rows=16):
+    r0, nr, c0, nc = b
+    Pr, Pc = P[r0:r0 + nr], P[c0:c0 + nc]
+    kmax = min(nr, nc, 1024)
+    Ua = np.zeros((nr, 64))
+    Va = np.zeros((nc, 64))
+    used_r = np.zeros(nr, dtype=bool)
+    used_c = np.zeros(nc, dtype=bool)
+    norm2, k, i, small = 0.0, 0, 0, 0
+    tol = eps / 16.0
+    while k < kmax:
+        if k == Ua.shape[1]:                       # grow the cross storage
+            Ua = np.hstack([Ua, np.zeros((nr, k))])
+            Va = np.hstack([Va, np.zeros((nc, k))])
+        used_r[i] = True
+        rv = kernel.offdiag(Pr[i:i + 1], Pc)[0] - Ua[i, :k] @ Va[:, :k].T
+        a = np.abs(rv)
+        a[used_c] = -1.0
+        j = int(np.argmax(a))
+        if a[j] <= 0.0:                            # zero residual row: try another row
+            free = np.flatnonzero(~used_r)
+            if free.size == 0:
+                break
+            i = int(free[0])
+            continue
+        v = rv / rv[j]
+        u = kernel.offdiag(Pr, Pc[j:j + 1])[:, 0] - Ua[:, :k] @ Va[j, :k]
+        used_c[j] = True
+        uu, vv = float(u @ u), float(v @ v)
+        norm2 += 2.0 * float((Ua[:, :k].T @ u) @ (Va[:, :k].T @ v)) + uu * vv
+        Ua[:, k], Va[:, k] = u, v
+        k += 1
+        if np.sqrt(uu * vv) <= tol * np.sqrt(max(norm2, 0.0)):
+            small += 1
+            if small >= 2:
+                break
+        else:
+            small = 0
+        au = np.abs(u)
+        au[used_r] = -1.0
+        i = int(np.argmax(au))
+        if au[i] < 0.0:
+            break
+    Ua, Va = Ua[:, :k], Va[:, :k]
+    # recompress: B ~ Ua Va^T = Qu (Ru Rv^T) Qv^T
+    Qu, Ru = np.linalg.qr(Ua)
+    Qv, Rv = np.linalg.qr(Va)
+    W, s, Zt = np.linalg.svd(Ru @ Rv.T)
+    # sampled rows: the residual of the full cross approximation
+    ii = rng.integers(0, nr, min(sample_rows, nr))
+    R = kernel.offdiag(Pr[ii], Pc) - Ua[ii] @ Va.T
+    nb2 = float(np.sum(s * s))
+    res2 = float(np.sum(R * R)) * nr / len(ii)
+    p = _rank(s, eps, rule, nb2 + res2, norm_a_2, res2)
+    if p is None:
+        p = len(s)
+    U = Qu @ W[:, :p]
+    Z = Qv @ Zt[:p].T
+    cert = np.sqrt(res2 / max(nb2, 1e-300))
+    return U, s[:p].copy(), Z, nb2, k, cert
+
+
 def compress(kernel, P, blocks, leaves, eps, rule="frob", norm_a_2=None,
-             seed=12345, dense_limit=512 * 512, workers=None) -> Compressed:
+             seed=12345, dense_limit=512 * 512, workers=None, method="random") -> Compressed:
     """Compress every off-diagonal block of the kernel matrix over ``P``.
 
     ``blocks``: (row0, nrows, col0, ncols) per off-diagonal block in the
@@ -153,6 +226,7 @@ def compress(kernel, P, blocks, leaves, eps, rule="frob", norm_a_2=None,
     nb = len(blocks)
     U, S, Z, nb2 = [None] * nb, [None] * nb, [None] * nb, np.zeros(nb)
     sk = [0] * nb
+    cert = [0.0] * nb
     pool = _Pool(workers)
     rng = np.random.default_rng(seed)
     twin = {}                      # lower block j derived from upper block i
@@ -169,17 +243,24 @@ def compress(kernel, P, blocks, leaves, eps, rule="frob", norm_a_2=None,
         for i, res in zip(small, pool.map(
                 lambda i: _dense_block(kernel, P, blocks[i], eps, rule, norm_a_2), small)):
             U[i], S[i], Z[i], nb2[i] = res
-        prev_rank = 16
-        for i in large:
-            U[i], S[i], Z[i], nb2[i], sk[i] = _random_block(
-                kernel, P, blocks[i], eps, rule, norm_a_2, pool, rng, prev_rank + 16)
-            prev_rank = max(8, U[i].shape[1])
+        if method == "aca":
+            seeds = rng.integers(0, 2**31 - 1, len(large))
+            for i, res in zip(large, pool.map(
+                    lambda t: _aca_block(kernel, P, blocks[t[0]], eps, rule, norm_a_2,
+                                         np.random.default_rng(int(t[1]))), list(zip(large, seeds)))):
+                U[i], S[i], Z[i], nb2[i], sk[i], cert[i] = res
+        else:
+            prev_rank = 16
+            for i in large:
+                U[i], S[i], Z[i], nb2[i], sk[i] = _random_block(
+                    kernel, P, blocks[i], eps, rule, norm_a_2, pool, rng, prev_rank + 16)
+                prev_rank = max(8, U[i].shape[1])
     finally:
         if limiter is not None:
             limiter.restore_original_limits()
     sign = -1.0 if kernel.antisymmetric else 1.0
     for j, i in twin.items():
-        U[j], S[j], Z[j], nb2[j], sk[j] = Z[i], S[i], sign * U[i], nb2[i], sk[i]
+        U[j], S[j], Z[j], nb2[j], sk[j], cert[j] = Z[i], S[i], sign * U[i], nb2[i], sk[i], cert[i]
     Vs = [np.ascontiguousarray(z * s[None, :]) for z, s in zip(Z, S)]
     Us = [np.ascontiguousarray(u) for u in U]
     lv = []
@@ -189,4 +270,4 @@ def compress(kernel, P, blocks, leaves, eps, rule="frob", norm_a_2=None,
         leaf_n2 += float(np.sum(D * D))
         lv.append(D)
     pool.ex.shutdown()
-    return Compressed(n, lv, Us, Vs, float(leaf_n2 + nb2.sum()), nb2, sk)
+    return Compressed(n, lv, Us, Vs, float(leaf_n2 + nb2.sum()), nb2, sk, cert)

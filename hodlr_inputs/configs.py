@@ -17,7 +17,8 @@ right-hand sides.  Points use seed 0 and right-hand sides seed 1 of numpy's
 * ``c5`` -- n=2^20 points from a mixture of four Gaussians (centres 0.2,
   0.4, 0.6, 0.8, sd 0.02, clipped, sorted), 1/(|x_i-x_j|+1e-5) + n on the
   diagonal, depth 12 (leaf 256), eps=1e-10, formats {fp32, fp16}, fp64
-  accumulation, 16 fp64 right-hand sides ~ N(0,1).
+  accumulation, 16 fp64 right-hand sides ~ N(0,1); compressed by adaptive
+  cross approximation (too large to evaluate every entry).
 * ``mat1``..``mat4`` -- the paper's matrix-vector experiments (Sect. 4,
   kernels (4.1)): n=2000, depth 8; (i) on a 1D grid, (ii) and (iii) with
   h=1 and h=20 on a 40x50 grid of [-1,1]^2; x ~ U(-1,1); formats
@@ -84,10 +85,12 @@ def _c3(n=262144, depth=9):
 
 
 def _c5(n=1 << 20, depth=12):
+    # blocks far too large to evaluate whole: adaptive cross approximation
     return Config("c5" if n == 1 << 20 else f"c5_{n}", n, depth, lambda: Pt.clustered_1d(n, 0),
                   K.inv_dist_reg(1e-5, float(n)), 1e-10, "frob", ("fp32", "fp16"), (16,),
                   "fp64", "normal", acc="fp64",
-                  description="1/(r+1e-5)+n I, clustered 1D, high accuracy")
+                  description="1/(r+1e-5)+n I, clustered 1D, high accuracy",
+                  extra={"compress": "aca"})
 
 
 def _mat(i):
@@ -138,5 +141,6 @@ def build(cfg: Config, blocks, leaves, seed: int = 12345):
     """Points and the compressed operator over the caller's partition."""
     from .compress import compress
     P = cfg.points()
-    op = compress(cfg.kernel, P, blocks, leaves, cfg.eps, cfg.rule, norm_a_2(cfg, P), seed=seed)
+    op = compress(cfg.kernel, P, blocks, leaves, cfg.eps, cfg.rule, norm_a_2(cfg, P), seed=seed,
+                  method=cfg.extra.get("compress", "random"))
     return P, op

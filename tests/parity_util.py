@@ -33,7 +33,7 @@ class Case:
         if c.rule == "spec_global":
             na2 = float(np.linalg.norm(c.kernel.dense(self.P), 2))
         self.op = CP.compress(c.kernel, self.P, [(b.row0, b.nrows, b.col0, b.ncols) for b in self.blocks],
-                              self.leaves_b, self.eps, c.rule, na2)
+                              self.leaves_b, self.eps, c.rule, na2, method=c.extra.get("compress", "random"))
         self.norms2 = np.concatenate([[self.op.norm2_all], self.op.norm2_blocks])
 
     def oracle_assign(self, allowed):

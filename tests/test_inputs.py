@@ -62,6 +62,25 @@ def test_randomised_path_meets_rule(eps):
         assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-11)
 
 
+@pytest.mark.parametrize("eps", [1e-4, 1e-10])
+def test_cross_approximation_path_meets_rule(eps):
+    """method="aca" (used where blocks are too large to evaluate whole):
+    checked here against the dense blocks, where they can be formed."""
+    c = CF.get("c5_s")
+    n, depth = 4096, 3
+    P = c.points()[:n]
+    blks, lv = _part(n, depth)
+    op = CP.compress(c.kernel, P, blks, lv, eps, "frob", dense_limit=64 * 64, method="aca")
+    ref = CP.compress(c.kernel, P, blks, lv, eps, "frob")
+    A = c.kernel.dense(P)
+    for (r0, nr, c0, nc), U, V, p_ref in zip(blks, op.U, op.V, ref.ranks):
+        B = A[r0:r0 + nr, c0:c0 + nc]
+        assert np.linalg.norm(B - U @ V.T) <= 1.05 * eps * np.linalg.norm(B)
+        assert abs(U.shape[1] - p_ref) <= 1
+        assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
+    assert max(op.certificate) < eps
+
+
 def test_spec_global_config_c1_small():
     c = CF.get("c1_s")
     P = c.points()
