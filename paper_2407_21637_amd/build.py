@@ -5,7 +5,11 @@
 Compiles ``csrc/host.cpp`` (host core and C ABI) and ``csrc/kernels.hip``
 (device kernels) with hipcc and links them into
 ``paper_2407_21637_amd/libhodlr.so``.  Packed-fp32 instructions are turned
-off for the device code (``-packed-fp32-ops``).
+off for the device code (``-packed-fp32-ops``), and MFMA accumulators are
+kept in the architectural VGPRs (``-amdgpu-mfma-vgpr-form``): with the
+accumulators in AGPRs the compiler copied the leaf GEMM's accumulators
+between the two register files on every loop iteration and needed more
+registers in total (one wave per SIMD instead of two).
 """
 from __future__ import annotations
 
@@ -21,7 +25,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhodlr.so")
 ARCH = os.environ.get("HODLR_OFFLOAD_ARCH", "gfx950")
 
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def _hipcc():

@@ -1062,24 +1062,27 @@ struct XStage {                                     // this thread's share of on
     static constexpr int CW = 16 * NT;
     static constexpr int N = (CW * (kStep / 4) + kThreads - 1) / kThreads;   // 4-element pieces
     XT v[N][4];
+    bool in[N];
+    // Every lane loads (pieces outside the leaf or the column range read
+    // row 0 of column c0 instead and are zeroed when stored): with no
+    // branch around the loads, and nothing using their values before the
+    // MFMAs of the current step, the wait before those MFMAs leaves the
+    // step fetched ahead in flight.
     __device__ __forceinline__ void load(const XT* Xl, int64_t ldw, int k0, int mp, int c0, int nrhs) {
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const int e = threadIdx.x + kThreads * i;
             const int col = e >> 3, part = e & 7;    // 8 pieces of 4 rows per column
             const int k = k0 + 4 * part, c = c0 + col;
-            if (col < CW && k < mp && c < nrhs) {
-                const XT* src = Xl + k + ldw * c;
-                if constexpr (sizeof(XT) == 4) {
-                    const float4 a = *reinterpret_cast<const float4*>(src);
-                    v[i][0] = a.x; v[i][1] = a.y; v[i][2] = a.z; v[i][3] = a.w;
-                } else {
-                    const double2 a = reinterpret_cast<const double2*>(src)[0];
-                    const double2 b = reinterpret_cast<const double2*>(src)[1];
-                    v[i][0] = a.x; v[i][1] = a.y; v[i][2] = b.x; v[i][3] = b.y;
-                }
+            in[i] = col < CW && k < mp && c < nrhs;
+            const XT* src = Xl + (in[i] ? k + ldw * c : ldw * c0);
+            if constexpr (sizeof(XT) == 4) {
+                const float4 a = *reinterpret_cast<const float4*>(src);
+                v[i][0] = a.x; v[i][1] = a.y; v[i][2] = a.z; v[i][3] = a.w;
             } else {
-                v[i][0] = v[i][1] = v[i][2] = v[i][3] = XT(0);
+                const double2 a = reinterpret_cast<const double2*>(src)[0];
+                const double2 b = reinterpret_cast<const double2*>(src)[1];
+                v[i][0] = a.x; v[i][1] = a.y; v[i][2] = b.x; v[i][3] = b.y;
             }
         }
     }
@@ -1088,10 +1091,11 @@ struct XStage {                                     // this thread's share of on
         for (int i = 0; i < N; ++i) {
             const int e = threadIdx.x + kThreads * i;
             const int col = e >> 3, part = e & 7;
-            if (col < CW) {
+            // (the test is needed only when the block has more pieces than the step)
+            if (kThreads * N <= CW * 8 || col < CW) {
                 XT* dst = xs + col * kXLD + 4 * part;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) dst[r] = v[i][r];
+                for (int r = 0; r < 4; ++r) dst[r] = in[i] ? v[i][r] : XT(0);
             }
         }
     }
@@ -1099,12 +1103,19 @@ struct XStage {                                     // this thread's share of on
 
 struct LeafD {                                      // the lane's D values of one step
     double a0[kKL], a1[kKL];
+    // Branch-free like XStage::load, and the values are used as loaded:
+    // lanes past the leaf's columns read columns 0..7 instead, which meet
+    // the zero rows of the staged X; lanes of a row tile past the tile read
+    // tile row r & 15 (present: nr >= 16), and those accumulator rows are
+    // never written.  Either way the values are finite leaf entries.
     __device__ __forceinline__ void load(const double* Dp, int nr, int k, bool ok, bool act0, bool act1, int r0,
                                          int r1) {
+        const int kk = ok ? k : 0;
+        const int s0 = act0 ? r0 : (r0 & 15), s1 = act1 ? r1 : (r1 & 15);
 #pragma unroll
         for (int q = 0; q < kKL; ++q) {
-            a0[q] = (ok && act0) ? Dp[int64_t(k + q) * nr + r0] : 0.0;
-            a1[q] = (ok && act1) ? Dp[int64_t(k + q) * nr + r1] : 0.0;
+            a0[q] = Dp[int64_t(kk + q) * nr + s0];
+            a1[q] = Dp[int64_t(kk + q) * nr + s1];
         }
     }
 };
@@ -1206,24 +1217,30 @@ __device__ void run_expand_w(const KParams& kp, int tile, int yg, const XT* __re
         da.load(Dp, t.nr, kKL * g, kKL * g < L.mp, act0, act1, r0, r1);   // mp and k are multiples of 8
         xr.store(xs0);
         __syncthreads();
-        for (int s = 0; s < nstep; s += 2) {
-            const int k1 = (s + 1) * kStep, k2 = (s + 2) * kStep;
-            if (s + 1 < nstep) {
-                xr.load(Xl, ldw, k1, L.mp, c0, nrhs);
-                db.load(Dp, t.nr, k1 + kKL * g, k1 + kKL * g < L.mp, act0, act1, r0, r1);
-            }
+        // Steps go in pairs (X step s in xs0 / xs1 by parity, D in da / db)
+        // with one exit, and the step fetched ahead is issued
+        // unconditionally (after the last pair it re-reads the last step
+        // into buffers read again only by an odd count's final step), so
+        // every iteration issues the same loads and the wait before the
+        // MFMAs leaves the fetch ahead in flight.
+        const int last = (nstep - 1) * kStep;
+        int s = 0;
+        for (; s + 1 < nstep; s += 2) {
+            const int k1 = (s + 1) * kStep, k2 = min((s + 2) * kStep, last);
+            xr.load(Xl, ldw, k1, L.mp, c0, nrhs);
+            db.load(Dp, t.nr, k1 + kKL * g, k1 + kKL * g < L.mp, act0, act1, r0, r1);
             leaf_mma<XT, NT>(xs0, da, g, li, accd);
-            if (s + 1 < nstep) xr.store(xs1);
+            __builtin_amdgcn_sched_barrier(0);          // keep the store's zeroing after the MFMAs
+            xr.store(xs1);
             __syncthreads();
-            if (s + 1 >= nstep) break;
-            if (s + 2 < nstep) {
-                xr.load(Xl, ldw, k2, L.mp, c0, nrhs);
-                da.load(Dp, t.nr, k2 + kKL * g, k2 + kKL * g < L.mp, act0, act1, r0, r1);
-            }
+            xr.load(Xl, ldw, k2, L.mp, c0, nrhs);
+            da.load(Dp, t.nr, k2 + kKL * g, k2 + kKL * g < L.mp, act0, act1, r0, r1);
             leaf_mma<XT, NT>(xs1, db, g, li, accd);
-            if (s + 2 < nstep) xr.store(xs0);
+            __builtin_amdgcn_sched_barrier(0);
+            xr.store(xs0);
             __syncthreads();
         }
+        if (s < nstep) leaf_mma<XT, NT>(xs0, da, g, li, accd);   // odd count: the last step
     }
     // the depth ancestors' blocks whose rows contain this leaf (T staged
     // before the leaf GEMM is visible: its loop ended with a barrier)
@@ -1293,7 +1310,15 @@ __global__ __launch_bounds__(kThreads) void k_expand_w(KParams kp, const XT* __r
                                                        int jc) {
     extern __shared__ double smem_d[];
     __shared__ int s_off[kMaxDepth + 2];
-    run_expand_w<XT, AT, NT>(kp, blockIdx.x, blockIdx.y, Xw, ldw, Y, ldy, nrhs, lds_bytes, jc, smem_d, s_off);
+    // Block b runs tile 8 (b / 8 ncg) + b % 8, column group (b / 8) % ncg:
+    // consecutive blocks go to the 8 XCDs in turn, so the column groups of
+    // a tile run one after another on the same XCD and the second reads
+    // the tile's D from that XCD's L2.
+    const int ncg = (nrhs + 16 * NT - 1) / (16 * NT);
+    const int b = blockIdx.x;
+    const int tile = (b / (8 * ncg)) * 8 + (b & 7), cg = (b >> 3) % ncg;
+    if (tile >= kp.netiles) return;                     // whole block: before any barrier
+    run_expand_w<XT, AT, NT>(kp, tile, cg, Xw, ldw, Y, ldy, nrhs, lds_bytes, jc, smem_d, s_off);
 }
 
 template <typename XT, typename AT, int NT>
@@ -1319,7 +1344,8 @@ hipError_t launch_wide_nt(const KParams& kp, const XT* Xw, int64_t ldw, XT* Y, i
     int64_t lds = 0;
     if (!wide_lds(kp, CW, sizeof(XT), &jc, &lds)) return hipErrorInvalidConfiguration;
     tm.begin(2);
-    hipLaunchKernelGGL((k_expand_w<XT, AT, NT>), dim3(kp.netiles, (nrhs + CW - 1) / CW), dim3(kThreads),
+    hipLaunchKernelGGL((k_expand_w<XT, AT, NT>), dim3(8 * ((nrhs + CW - 1) / CW) * ((kp.netiles + 7) / 8)),
+                       dim3(kThreads),
                        size_t(lds), s, kp, Xw, ldw, Y, ldy, nrhs, int(lds), jc);
     tm.end(2);
     return hipGetLastError();
@@ -1343,8 +1369,7 @@ hipError_t launch_wide(const KParams& kp, const void* Xv, int64_t ldx, void* Yv,
     }
     if (nrhs <= 16) return launch_wide_nt<XT, AT, 1>(kp, Xw, ldw, Y, ldy, nrhs, tm);
     if (nrhs <= 32) return launch_wide_nt<XT, AT, 2>(kp, Xw, ldw, Y, ldy, nrhs, tm);
-    if (nrhs <= 64 || sizeof(XT) == 8) return launch_wide_nt<XT, AT, 4>(kp, Xw, ldw, Y, ldy, nrhs, tm);
-    return launch_wide_nt<XT, AT, 8>(kp, Xw, ldw, Y, ldy, nrhs, tm);
+    return launch_wide_nt<XT, AT, 4>(kp, Xw, ldw, Y, ldy, nrhs, tm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1474,8 +1499,7 @@ hipError_t batch_typed(const BatchGroup& g, hipStream_t s) {
     switch (g.rg) {
         case 1: return batch_wide<XT, AT, 1>(g, s);
         case 2: return batch_wide<XT, AT, 2>(g, s);
-        case 4: return batch_wide<XT, AT, 4>(g, s);
-        default: return batch_wide<XT, AT, 8>(g, s);
+        default: return batch_wide<XT, AT, 4>(g, s);
     }
 }
 
@@ -1520,8 +1544,8 @@ int plan_launch(const KParams& kp, const void* X, int64_t ldx, int nrhs, bool xy
         o.lds_contract = int64_t(lds_phase1(kp, rg));
         o.lds_expand = int64_t(lds_expand(kp, rg, acc_bytes));
     } else {
-        const int nt = nrhs <= 16 ? 1 : nrhs <= 32 ? 2 : (nrhs <= 64 || xy_double) ? 4 : 8;
-        const int ntc = nt > 4 ? 4 : nt;
+        const int nt = nrhs <= 16 ? 1 : nrhs <= 32 ? 2 : 4;
+        const int ntc = nt;
         const int cw = 16 * nt;
         const bool aligned = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((ldx * int64_t(xbytes)) % 16 == 0);
         o.wide = 1;
