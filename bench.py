@@ -44,23 +44,34 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_nrhs1.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2407_21637_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2407_21637_amd", "csrc")
+# device sources of each product path: a counter summary under profiles/
+# holds only while the hash of its path's sources is unchanged
+PATH_SOURCES = {"wave": ("hodlr_internal.h", "dev_common.h", "wave_path.h"),
+                "wide": ("hodlr_internal.h", "dev_common.h", "wave_path.h", "wide_path.h")}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_hash(path):
+    h = hashlib.sha256()
+    for f in PATH_SOURCES[path]:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
 
 
-def read_traffic():
+def traffic_file(workload, nrhs):
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}_nrhs{nrhs}.txt")
+
+
+def read_traffic(workload, nrhs):
     """key: value lines of the counter summary (HBM bytes per launch)."""
     out = {}
-    if os.path.exists(TRAFFIC_FILE):
-        for line in open(TRAFFIC_FILE):
+    f = traffic_file(workload, nrhs)
+    if os.path.exists(f):
+        for line in open(f):
             k, sep, v = line.partition(":")
             if sep and k.strip() and " " not in k.strip():
                 out[k.strip()] = v.strip()
@@ -338,6 +349,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the timed products (for running under rocprofv3)")
+    ap.add_argument("--kernel-hash", action="store_true",
+                    help="print the source hash of each product path and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device-to-device copy 5 times (counter calibration) and exit")
     args = ap.parse_args()
@@ -346,6 +359,9 @@ def main():
                                    "small exchange of T (see DESIGN.md), which is not implemented; "
                                    "run with --gpus 1"}), flush=True)
         sys.exit(2)
+    if args.kernel_hash:
+        print(json.dumps({k: kernel_hash(k) for k in PATH_SOURCES}))
+        return
 
     # torch first: the library then binds to the HIP runtime torch loaded
     import torch
@@ -416,8 +432,8 @@ def main():
     con_us = r["phases"].get("contract", 0.0)
     wide = nrhs0 >= 8
     traffic = traffic_c = None
-    tr = read_traffic()
-    if tr.get("kernel_sha") == kernel_hash() and tr.get("workload") == cfg.name and \
+    tr = read_traffic(cfg.name, nrhs0)
+    if tr.get("kernel_sha") == kernel_hash("wide" if wide else "wave") and tr.get("workload") == cfg.name and \
             tr.get("nrhs") == str(nrhs0):
         traffic = int(tr.get("second_launch_bytes", 0)) or None
         traffic_c = int(tr.get("first_launch_bytes", 0)) or None

@@ -4,7 +4,8 @@
 
 Compiles ``csrc/host.cpp`` (host core and C ABI) and ``csrc/kernels.hip``
 (device kernels) with hipcc and links them into
-``paper_2407_21637_amd/libhodlr.so``.  Packed-fp32 instructions are turned
+``paper_2407_21637_amd/libhodlr.so``, and ``csrc/calibrate.hip`` (the
+machine-ceiling probe) into ``paper_2407_21637_amd/calibrate``.  Packed-fp32 instructions are turned
 off for the device code (``-packed-fp32-ops``), and MFMA accumulators are
 kept in the architectural VGPRs (``-amdgpu-mfma-vgpr-form``): with the
 accumulators in AGPRs the compiler copied the leaf GEMM's accumulators
@@ -23,6 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhodlr.so")
+CALIBRATE = os.path.join(HERE, "calibrate")
 ARCH = os.environ.get("HODLR_OFFLOAD_ARCH", "gfx950")
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -59,6 +61,13 @@ def build(verbose: bool = False) -> str:
               "-lpthread"])
         shutil.copyfile(tmp_lib, LIB + ".tmp")
         os.replace(LIB + ".tmp", LIB)
+        # the machine-ceiling probe (a standalone program, not linked into the library)
+        tmp_cal = os.path.join(tmp, "calibrate")
+        _run([hipcc, "-std=c++17", "-O3", f"--offload-arch={ARCH}", *DEVICE_FLAGS,
+              os.path.join(CSRC, "calibrate.hip"), "-o", tmp_cal])
+        shutil.copyfile(tmp_cal, CALIBRATE + ".tmp")
+        os.chmod(CALIBRATE + ".tmp", 0o755)
+        os.replace(CALIBRATE + ".tmp", CALIBRATE)
     if verbose:
         print("built", LIB)
     return LIB
