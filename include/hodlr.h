@@ -184,14 +184,28 @@ hodlr_status hodlr_get_block(hodlr_op op, int32_t block, hodlr_block_info* info)
 hodlr_status hodlr_export_block(hodlr_op op, int32_t block, void* u_codes, int8_t* u_exp,
                                 void* v_codes, int8_t* v_exp, int32_t from_device);
 
-/* Y = A_H X (Alg. "HODLR_MATVEC").  xy_dtype is HODLR_FP32 or HODLR_FP64
- * for both X and Y.  Leaf products D_i X_i run in fp64; a level stored in
- * fp64 runs in fp64; other levels run in the accumulation precision, with
- * the stored codes converted in registers.  With nrhs < 8 the products
- * are wavefront reductions (HBM-bound); with nrhs >= 8 they run on the
- * matrix cores (fp64 MFMA for leaves and fp64 levels, fp32 MFMA for the
- * others).  stream is a hipStream_t (NULL: the default stream).  The call
- * only enqueues work; on first use with a larger nrhs it may allocate (and
+/* Y = A_H X (Alg. "HODLR_MATVEC").  xy_dtype is the dtype of both X and Y.
+ *
+ * HODLR_FP64 or HODLR_FP32: leaf products D_i X_i run in fp64; a level
+ * stored in fp64 runs in fp64; other levels run in the accumulation
+ * precision, with the stored codes converted in registers.  With nrhs < 8
+ * the products are wavefront reductions (HBM-bound); with nrhs >= 8 they
+ * run on the matrix cores (fp64 MFMA for leaves and fp64 levels, fp32 MFMA
+ * for the others).
+ *
+ * HODLR_BF16 or HODLR_FP16: the product in that low working precision W
+ * (Thm. 3.5 and the Sect. 4 experiment with u = u_W): the leaves (a W copy
+ * made on the first such call), every stored generator value and T_b =
+ * V_b^T X enter the arithmetic rounded to W (nearest even), products are
+ * summed in fp32 on the matrix cores (v_mfma_f32_16x16x32_bf16 / _f16),
+ * and Y is rounded to W once.  Any nrhs >= 1.  For fp16 a leaf entry or a
+ * generator stored in fp64/fp32/bf16 outside the fp16 range gives
+ * HODLR_E_RANGE (narrow stored formats are column-scaled into range); a
+ * T_b or Y entry beyond the range becomes infinite.  Not available in
+ * hodlr_matvec_batched.
+ *
+ * stream is a hipStream_t (NULL: the default stream).  The call only
+ * enqueues work; on first use with a larger nrhs it may allocate (and
  * synchronise for) a bigger workspace. */
 hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int64_t ldy,
                           int32_t nrhs, int32_t xy_dtype, void* stream);

@@ -27,6 +27,9 @@ Modules, each citing the passage it follows:
                   scales for the narrow formats.
 * ``matvec``   -- HODLR_MATVEC (Alg. "HODLR_MATVEC"), its absolute-value
                   twin and a dense assembly of the stored operator.
+* ``lowp``     -- the product in a low working precision (bf16, fp16): the
+                  Thm. 3.5 / Sect. 4 setting with u = u_W, operands rounded
+                  to W, and its componentwise tolerance.
 * ``bounds``   -- the error bounds of Thm. 3.1 / eqs. (3.4)-(3.7) and
                   Thm. 3.5, and the componentwise tolerance used to compare
                   the GPU result with this oracle.

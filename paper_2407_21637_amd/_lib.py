@@ -244,16 +244,16 @@ class Operator:
         return uc, ue[:p].astype(np.int64), vc, ve[:p].astype(np.int64)
 
     def matvec(self, X, Y=None, stream=None):
-        """Y = A_H X for torch tensors on the operator's GPU (fp32 or fp64);
-        X is (n,) or (n, nrhs) column-major.  Returns Y (allocated if None)."""
+        """Y = A_H X for torch tensors on the operator's GPU; X is (n,) or
+        (n, nrhs) column-major.  float64 / float32 X: the product as
+        hodlr_matvec defines it for those dtypes; bfloat16 / float16 X: the
+        product in that low working precision.  Returns Y (allocated if None)."""
         import torch
         xp, ldx, nrhs = _colmajor(X, self.n)
-        if X.dtype == torch.float32:
-            code = 1
-        elif X.dtype == torch.float64:
-            code = 0
-        else:
-            raise TypeError("X must be float32 or float64")
+        codes = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2, torch.float16: 3}
+        if X.dtype not in codes:
+            raise TypeError("X must be float64, float32, bfloat16 or float16")
+        code = codes[X.dtype]
         if Y is None:
             Y = torch.empty(self.n, dtype=X.dtype, device=X.device) if X.dim() == 1 else \
                 colmajor_empty(self.n, nrhs, X.dtype, X.device)

@@ -71,6 +71,8 @@ struct BlockDesc {        // one per off-diagonal block, canonical order
     int32_t item0;        // first contraction item of this block
     int32_t nitems;       // number of contraction items
     int32_t pad_;         // rows of a contraction item (V panel chunk)
+    int64_t tw_off;       // low working precision: offset of T_b in W, in units of
+                          // round_up(rank, 32) (x nrhs values, [c][j])
 };
 
 struct LeafDesc {
@@ -106,6 +108,8 @@ struct KParams {
     const CItem* citems;
     const ETile* etiles;
     const double* tscale;
+    const void* leafw;           // low working precision: the leaves rounded to W, row-major (ld = mp)
+    void* Tw;                    // low working precision: T_b in W (sum of round_up(rank, 32) * nrhs)
     double* partial;             // workspace: sum over items of rank * nrhs
     double* T;                   // workspace: sum over blocks of rank * nrhs
     void* xpad;                  // workspace: padded copy of X (npad * nrhs), if needed
@@ -145,6 +149,11 @@ constexpr int kPhases = 4;     // padded X copy, contraction, expansion, reducti
 int launch_matvec(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_t ldy,
                   int nrhs, bool xy_double, bool acc_double, void* stream, void* const* events,
                   bool* ran);
+
+// low working precision (w = 0: bf16, 1: fp16): X and Y in W, every operand
+// rounded to W, fp32 accumulation on the matrix cores
+int launch_matvec_lp(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs, int w,
+                     void* stream, void* const* events, bool* ran);
 
 // ---------------------------------------------------------------------------
 // batched products: persistent launches over many operators

@@ -223,8 +223,9 @@ struct Workspace {
     double* T = nullptr;
     void* xpad = nullptr;
     double* W = nullptr;       // leaf products of the wave path
+    void* Tw = nullptr;        // T_b in a low working precision
     int32_t* sync = nullptr;   // counters of the fused launch; zeroed once, self-resetting
-    int64_t cap_partial = 0, cap_T = 0, cap_xpad = 0, cap_sync = 0, cap_W = 0;
+    int64_t cap_partial = 0, cap_T = 0, cap_xpad = 0, cap_sync = 0, cap_W = 0, cap_Tw = 0;
     uint64_t gen = 0;          // bumped whenever a buffer is replaced (batched plans keep pointers)
 };
 
@@ -261,6 +262,7 @@ struct hodlr_op_s {
     std::vector<ETile> etiles;
     int64_t fac_bytes = 0;     // device factor buffer size
     int64_t total_rank = 0;    // sum of ranks (T slots)
+    int64_t total_rank32 = 0;  // sum of ranks rounded up to 32 (T slots in a low working precision)
     int64_t total_item_rank = 0;
     int64_t codes_bytes = 0;   // sum (r+c) p s(f)
     int64_t scaled_cols = 0;
@@ -274,6 +276,7 @@ struct hodlr_op_s {
     int device = -1;
     uint8_t* d_fac = nullptr;
     double* d_leaf = nullptr;
+    void* d_leafw[2] = {nullptr, nullptr};     // the leaves rounded to bf16 / fp16, made on first use
     BlockDesc* d_blocks = nullptr;
     LeafDesc* d_leaves = nullptr;
     CItem* d_citems = nullptr;
@@ -321,6 +324,9 @@ void free_device(hodlr_op_s* op) {
     free_profile(op);
     dev_free(op->d_fac);
     dev_free(op->d_leaf);
+    dev_free(op->d_leafw[0]);
+    dev_free(op->d_leafw[1]);
+    op->d_leafw[0] = op->d_leafw[1] = nullptr;
     dev_free(op->d_blocks);
     dev_free(op->d_leaves);
     dev_free(op->d_citems);
@@ -338,6 +344,7 @@ void free_device(hodlr_op_s* op) {
         dev_free(kv.second.T);
         dev_free(kv.second.xpad);
         dev_free(kv.second.W);
+        dev_free(kv.second.Tw);
         dev_free(kv.second.sync);
     }
     op->ws.clear();
@@ -462,7 +469,7 @@ hodlr_status pack(hodlr_op_s* op) {
     const int nb = op->nb;
     op->bdesc.assign(nb, BlockDesc{});
     op->citems.clear();
-    int64_t off = 0, toff = 0, poff = 0;
+    int64_t off = 0, toff = 0, poff = 0, twoff = 0;
     op->codes_bytes = 0;
     op->scaled_cols = 0;
     std::vector<int64_t> ts_off(nb);
@@ -490,6 +497,8 @@ hodlr_status pack(hodlr_op_s* op) {
         off = align_up(off + vpr * p * fmt_bytes(f), kPanelAlign);
         d.t_off = toff;
         toff += p;
+        d.tw_off = twoff;
+        twoff += (p + 31) / 32 * 32;
         d.ts_off = ts_total;
         ts_off[b] = ts_total;
         ts_total += p;
@@ -513,6 +522,7 @@ hodlr_status pack(hodlr_op_s* op) {
     }
     op->fac_bytes = std::max<int64_t>(off, kPanelAlign);
     op->total_rank = toff;
+    op->total_rank32 = twoff;
     op->total_item_rank = poff;
     op->max_items_rank = 0;
     for (int b = 0; b < nb; ++b)
@@ -1026,7 +1036,58 @@ hodlr_status hodlr_export_block(hodlr_op op, int32_t block, void* u_codes, int8_
 
 namespace {
 
-hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_double, KParams* kp,
+// The leaves rounded (nearest even) to the working precision w (HODLR_BF16
+// or HODLR_FP16), row-major per leaf (ld = mp, zero padding), uploaded on
+// first use.  For fp16 every leaf entry and every factor value stored in a
+// format wider than fp16's range (fp64, fp32, bf16) must be finite in fp16
+// (E_RANGE otherwise); the narrow stored formats are scaled into range.
+hodlr_status ensure_leaves_w(hodlr_op_s* op, int32_t w) {
+    const int slot = w == HODLR_BF16 ? 0 : 1;
+    if (op->d_leafw[slot]) return HODLR_OK;
+    const int f = w == HODLR_BF16 ? BF16 : F16;
+    if (f == F16) {
+        for (int b = 0; b < op->nb; ++b) {
+            const int32_t bf = op->bdesc[size_t(b)].fmt;
+            if (bf != F64 && bf != F32 && bf != BF16) continue;
+            for (const std::vector<double>* Fm : {&op->U[size_t(b)], &op->V[size_t(b)]})
+                for (double v : *Fm) {
+                    bool ovf = false;
+                    (void)encode_rne(v, F16, &ovf);
+                    if (ovf) return fail(HODLR_E_RANGE, "block %d has a generator value outside the fp16 range", b);
+                }
+        }
+    }
+    int64_t total = 0;
+    for (const LeafDesc& L : op->ldesc) total += int64_t(L.mp) * L.mp;
+    std::vector<uint16_t> img;
+    try {
+        img.assign(size_t(std::max<int64_t>(total, 1)), 0);
+    } catch (const std::bad_alloc&) {
+        return fail(HODLR_E_NOMEM, "host staging of the leaves in the working precision");
+    }
+    std::atomic<int> bad{-1};
+    parallel_for(op->nleaves, [&](int64_t i) {
+        const LeafDesc& L = op->ldesc[size_t(i)];
+        uint16_t* out = img.data() + L.d_off;
+        for (int64_t r = 0; r < L.m; ++r)
+            for (int64_t c = 0; c < L.m; ++c) {
+                bool ovf = false;
+                out[r * L.mp + c] = uint16_t(encode_rne(op->D[size_t(i)][size_t(c * L.m + r)], f, &ovf));
+                if (ovf) bad.store(int(i));
+            }
+    });
+    if (bad.load() >= 0)
+        return fail(HODLR_E_RANGE, "leaf %d has an entry outside the range of the working precision", bad.load());
+    hipError_t e = hipSetDevice(op->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    uint16_t* d = nullptr;
+    hodlr_status r = upload(&d, img.data(), img.size(), "leaves in the working precision");
+    if (r != HODLR_OK) return r;
+    op->d_leafw[slot] = d;
+    return HODLR_OK;
+}
+
+hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, int xy_bytes, KParams* kp,
                                uint64_t* ws_gen = nullptr) {
     std::lock_guard<std::mutex> lk(op->ws_mu);
     Workspace& w = op->ws[stream];
@@ -1034,7 +1095,9 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
     const int64_t need_t = std::max<int64_t>(1, op->total_rank * nrhs);
     // padded X: when some leaf is padded, and for the matrix-core path (nrhs >= kWideMin),
     // which reads X with 16-byte vector loads and copies it when it is not aligned
-    const int64_t need_x = (op->padded || nrhs >= kWideMin) ? op->npad * nrhs * (xy_double ? 8 : 4) : 0;
+    // (the low working precision path, 2-byte X, always runs on the matrix cores)
+    const bool lowp = xy_bytes == 2;
+    const int64_t need_x = (op->padded || nrhs >= kWideMin || lowp) ? op->npad * nrhs * xy_bytes : 0;
     auto grow = [&](void** ptr, int64_t* cap, int64_t bytes, const char* what) -> hodlr_status {
         if (bytes <= *cap) return HODLR_OK;
         if (*ptr) {
@@ -1059,9 +1122,11 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
         return r;
     if ((r = grow(reinterpret_cast<void**>(&w.T), &w.cap_T, need_t * 8, "T")) != HODLR_OK) return r;
     if (need_x && (r = grow(&w.xpad, &w.cap_xpad, need_x, "padded X")) != HODLR_OK) return r;
-    const int64_t need_w = nrhs < kWideMin ? op->npad * nrhs * 8 : 0;
+    const int64_t need_w = (nrhs < kWideMin && !lowp) ? op->npad * nrhs * 8 : 0;
     if (need_w && (r = grow(reinterpret_cast<void**>(&w.W), &w.cap_W, need_w, "leaf products")) != HODLR_OK)
         return r;
+    const int64_t need_tw = lowp ? std::max<int64_t>(1, op->total_rank32 * nrhs) * 2 : 0;
+    if (need_tw && (r = grow(&w.Tw, &w.cap_Tw, need_tw, "T in the working precision")) != HODLR_OK) return r;
     const int64_t need_s = sync_words(op->nb) * int64_t(sizeof(int32_t));
     if (need_s > w.cap_sync) {
         if ((r = grow(reinterpret_cast<void**>(&w.sync), &w.cap_sync, need_s, "counters")) != HODLR_OK) return r;
@@ -1080,6 +1145,7 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, bool xy_d
     kp->T = w.T;
     kp->xpad = w.xpad;
     kp->W = w.W;
+    kp->Tw = w.Tw;
     kp->sync = w.sync;
     kp->npad = op->npad;
     kp->max_leaf = op->max_leaf;
@@ -1176,7 +1242,7 @@ hodlr_status build_plan(const hodlr_op* ops, int count, const void* const* X, co
         hodlr_op op = ops[i];
         const bool xyd = xy_dtype[i] == HODLR_FP64;
         KParams kp{};
-        hodlr_status r = prepare_workspace(op, stream, nrhs[i], xyd, &kp);
+        hodlr_status r = prepare_workspace(op, stream, nrhs[i], xyd ? 8 : 4, &kp);
         if (r != HODLR_OK) return r;
         OpLaunch ol{};
         if (plan_launch(kp, X[i], ldx[i], nrhs[i], xyd, op->acc_double, &ol) != 0)
@@ -1392,7 +1458,7 @@ hodlr_status batch_run(const hodlr_op* ops, int count, const void* const* X, con
                                            "outside capture first", i);
             wg = it->second.gen;
         } else {
-            hodlr_status r = prepare_workspace(ops[i], stream, nrhs[i], xy_dtype[i] == HODLR_FP64, &kp, &wg);
+            hodlr_status r = prepare_workspace(ops[i], stream, nrhs[i], xy_dtype[i] == HODLR_FP64 ? 8 : 4, &kp, &wg);
             if (r != HODLR_OK) return r;
         }
         key.insert(key.end(), {ops[i]->uid, ops[i]->gen, wg, uint64_t(reinterpret_cast<uintptr_t>(X[i])),
@@ -1442,15 +1508,20 @@ hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int6
     if (!op) return fail(HODLR_E_ARG, "op is NULL");
     if (op->device < 0) return fail(HODLR_E_STATE, "host-only handle: no product");
     if (nrhs < 1) return fail(HODLR_E_ARG, "nrhs must be >= 1");
-    if (xy_dtype != HODLR_FP32 && xy_dtype != HODLR_FP64)
-        return fail(HODLR_E_UNSUPPORTED, "X/Y dtype must be HODLR_FP32 or HODLR_FP64");
+    const bool lowp = xy_dtype == HODLR_BF16 || xy_dtype == HODLR_FP16;
+    if (xy_dtype != HODLR_FP32 && xy_dtype != HODLR_FP64 && !lowp)
+        return fail(HODLR_E_UNSUPPORTED, "X/Y dtype must be HODLR_FP64, HODLR_FP32, HODLR_BF16 or HODLR_FP16");
     if (!X || !Y) return fail(HODLR_E_ARG, "X or Y is NULL");
     if (ldx < op->n || ldy < op->n) return fail(HODLR_E_ARG, "ldx and ldy must be >= n");
     hipError_t e = hipSetDevice(op->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     KParams kp{};
-    hodlr_status r = prepare_workspace(op, stream, nrhs, xy_dtype == HODLR_FP64, &kp);
+    const int xy_bytes = xy_dtype == HODLR_FP64 ? 8 : xy_dtype == HODLR_FP32 ? 4 : 2;
+    hodlr_status r;
+    if (lowp && (r = ensure_leaves_w(op, xy_dtype)) != HODLR_OK) return r;
+    r = prepare_workspace(op, stream, nrhs, xy_bytes, &kp);
     if (r != HODLR_OK) return r;
+    if (lowp) kp.leafw = op->d_leafw[xy_dtype == HODLR_BF16 ? 0 : 1];
     void* const* ev = nullptr;
     bool ran[kPhases] = {false, false, false, false};
     int32_t slot = -1;
@@ -1458,8 +1529,9 @@ hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int6
         slot = op->prof_used++;
         ev = reinterpret_cast<void* const*>(op->prof_ev.data() + size_t(slot) * 2 * kPhases);
     }
-    const int he = launch_matvec(kp, X, ldx, Y, ldy, nrhs, xy_dtype == HODLR_FP64, op->acc_double, stream,
-                                 ev, ran);
+    const int he = lowp ? launch_matvec_lp(kp, X, ldx, Y, ldy, nrhs, xy_dtype == HODLR_BF16 ? 0 : 1, stream, ev, ran)
+                        : launch_matvec(kp, X, ldx, Y, ldy, nrhs, xy_dtype == HODLR_FP64, op->acc_double, stream,
+                                        ev, ran);
     if (he == int(hipErrorInvalidConfiguration))
         return fail(HODLR_E_UNSUPPORTED, "leaf size %d with path rank %d needs more than 64 KB of LDS",
                     op->max_leaf, op->max_rank_path);

@@ -25,9 +25,12 @@
 // wide_path.h).  Batched products run the same device code from persistent
 // kernels (section "batched products" below).
 //
+// Low working precision (X and Y in bf16 or fp16): k_contract_lp,
+// k_reduce_lp, k_expand_lp (lowp_path.h).
+//
 // Layout of the sources: dev_common.h (codecs, wave sums, coherent
-// accesses), wave_path.h, wide_path.h, and this file (batched kernels and
-// the launch entry points), one translation unit.
+// accesses), wave_path.h, wide_path.h, lowp_path.h, and this file (batched
+// kernels and the launch entry points), one translation unit.
 //
 // Stored codes are converted in registers (Sect. 3.3: low-precision
 // storage cast to the working precision on the fly).
@@ -40,6 +43,7 @@
 #include "dev_common.h"
 #include "wave_path.h"
 #include "wide_path.h"
+#include "lowp_path.h"
 
 namespace hodlr {
 namespace {
@@ -198,6 +202,14 @@ int launch_matvec(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_
     return int(e);
 }
 
+
+int launch_matvec_lp(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs, int w,
+                     void* stream, void* const* events, bool* ran) {
+    const Timer tm{events, ran, static_cast<hipStream_t>(stream)};
+    const hipError_t e = w == 0 ? launch_lp<__bf16>(kp, X, ldx, Y, ldy, nrhs, tm)
+                                : launch_lp<_Float16>(kp, X, ldx, Y, ldy, nrhs, tm);
+    return int(e);
+}
 
 int plan_launch(const KParams& kp, const void* X, int64_t ldx, int nrhs, bool xy_double, bool acc_double,
                 OpLaunch* out) {
