@@ -206,6 +206,114 @@ def cpu_baseline(cfg, blocks, leaves, op, level_fmt, B_alg, X, budget_s=12.0):
                       f"on the same stored operator, {sec * 1e3:.1f} ms each"}, y, U, V, oblocks, lb
 
 
+BF16_PEAK_TFLOPS = 2500.0     # dense bf16 / fp16 MFMA
+
+
+def main_lowp(args, torch, H, cfg, h, op, fmts, nrhs):
+    """The product in a low working precision W on the workload's operator:
+    one JSON line; the roofline is the expansion launch (the W leaf GEMM,
+    HBM-bound below the W ridge of 2500 TFLOP/s / 8 TB/s ~ 312 flop/B)."""
+    w = args.working
+    wdt = torch.bfloat16 if w == "bf16" else torch.float16
+    inf = h.info()
+    leaf_w = inf["leaf_bytes"] // 4                      # the W copy of the leaves
+    ub = vb = lr = tw = 0
+    for b in range(h.nblocks):
+        bi = h.block(b)
+        sb = SBYTES[bi["dtype"]]
+        ub += bi["nrows"] * bi["rank"] * sb
+        vb += bi["ncols"] * bi["rank"] * sb
+        lr += (bi["nrows"] + bi["ncols"]) * bi["rank"]
+        tw += -(-bi["rank"] // 32) * 32 * nrhs * 2
+    n = cfg.n
+    B = leaf_w + inf["factor_bytes"] + inf["scale_bytes"] + n * nrhs * 2 * 2
+    LF = 2 * nrhs * (inf["leaf_bytes"] // 8)
+    Fl = LF + 2 * nrhs * lr
+    EB = leaf_w + ub + tw + n * nrhs * 2 * 2             # expansion: leaves, U, T, X, Y
+    CB = vb + n * nrhs * 2                               # contraction: V, X
+    Xh = cfg.X(nrhs)
+    from oracle import formats as OF
+    Xw = OF.round_rne(w, Xh)
+    X = H.colmajor_empty(n, nrhs, wdt, "cuda:0")
+    X.copy_(torch.from_numpy(np.asfortranarray(Xw)).to(wdt))
+    Y = H.colmajor_empty(n, nrhs, wdt, "cuda:0")
+    ms = time_steps(lambda: h.matvec(X, Y), args.steps, args.warmup, torch)
+    ph = time_phases(h, X, Y, 50, torch)
+    cold = time_cold(lambda: h.matvec(X, Y), 10, torch)
+    log(f"[bench] {w} working precision, nrhs={nrhs}: {ms * 1e3:.1f} us/step, {B / ms / 1e6:.1f} GB/s, "
+        f"cold {cold * 1e3:.1f} us, kernels (us) {ph}")
+    # the fp32/fp64 path on the same operator and X for the speedup
+    xdt = torch.float32 if cfg.x_dtype == "fp32" else torch.float64
+    Xf = H.colmajor_empty(n, nrhs, xdt, "cuda:0")
+    Xf.copy_(torch.from_numpy(np.asfortranarray(Xw)).to(xdt))
+    Yf = H.colmajor_empty(n, nrhs, xdt, "cuda:0")
+    ms_full = time_steps(lambda: h.matvec(Xf, Yf), args.steps, args.warmup, torch)
+    log(f"[bench] same product with {cfg.x_dtype} X: {ms_full * 1e3:.1f} us/step")
+    exp_us = ph["expand"]
+    exp_gbs = EB / (exp_us * 1e-6) / 1e9
+    intensity = LF / EB
+    if intensity >= BF16_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
+        ach = LF / (exp_us * 1e-6) / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / BF16_PEAK_TFLOPS, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(exp_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(exp_gbs / HBM_PEAK_GBS, 4)}
+    roof.update({"kernel": f"k_expand_lp ({w} MFMA leaf GEMM + low-rank, writes Y)", "traffic": None,
+                 "alg_bytes_per_launch": int(EB), "intensity_flop_per_byte": round(intensity, 2),
+                 "mfma_tflops": round(LF / (exp_us * 1e-6) / 1e12, 2), "mean_launch_us": round(exp_us, 2)})
+    value = B / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "HODLR matvec GB/s & Gflop/s (% roofline); speedup mixed vs FP64 at fixed eps",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": w, "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.description}; n={n}, depth {cfg.depth}, eps={cfg.eps:g}, "
+                               f"formats {fmts}, {w} working precision, nrhs={nrhs}",
+                   "n": n, "depth": cfg.depth, "eps": cfg.eps, "nrhs": nrhs, "formats": fmts,
+                   "working_precision": w},
+        "gflops": round(Fl / (ms * 1e-3) / 1e9, 2), "alg_bytes": int(B), "alg_flops": int(Fl),
+        "cold_cache_gbs": round(B / (cold * 1e-3) / 1e9, 2),
+        "speedup_vs_full_precision_path": round(ms_full / ms, 3),
+        "kernels_us": {k: round(v, 2) for k, v in ph.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        # the oracle's W product on a column sample: timing and the tolerance check
+        from oracle import lowp as LP
+        from oracle import quantize as Q
+        from oracle import tree as T
+        from oracle import bounds as BD
+        oblocks = T.blocks(n, cfg.depth)
+        lb = T.leaves(n, cfg.depth)
+        QU = [Q.quantize(u, fmts[b.level - 1]) for b, u in zip(oblocks, op.U)]
+        QV = [Q.quantize(v, fmts[b.level - 1]) for b, v in zip(oblocks, op.V)]
+        k = min(nrhs, 4)
+        t0 = time.perf_counter()
+        prod = LP.matvec_lowp(n, oblocks, lb, op.leaves, QU, QV, Xw[:, :k], w)
+        sec = time.perf_counter() - t0
+        Bk = leaf_w + inf["factor_bytes"] + inf["scale_bytes"] + n * k * 2 * 2
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:  # pragma: no cover
+            threads = 1
+        out["cpu_baseline"] = {"value": round(Bk / sec / 1e9, 4), "unit": "GB/s", "cores": int(threads),
+                               "kind": "oracle",
+                               "sample": f"one {w} product of the oracle (n={n}, nrhs={k}), {sec * 1e3:.1f} ms"}
+        h.matvec(X, Y)
+        torch.cuda.synchronize()
+        yg = Y[:, :k].float().cpu().double().numpy()
+        M = BD.chain_length(oblocks, op.ranks, [m for _, m in lb], cfg.depth)
+        tol = LP.tolerance(prod, w, M, max(b.ncols for b in oblocks))
+        err = np.abs(yg - prod.y)
+        out["check"] = {"max_err_over_tol": float((err / np.where(tol > 0, tol, 1)).max()),
+                        "rel_err_vs_oracle": float(np.linalg.norm(err) / np.linalg.norm(prod.y))}
+        if (err > tol).any():
+            log(f"[bench] {int((err > tol).sum())} entries outside the tolerance")
+    print(json.dumps(out), flush=True)
+
+
 def build_batch(name):
     """Compress a batched workload over the library's partitions (host, untimed)."""
     from hodlr_inputs import batch as BT
@@ -349,6 +457,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the timed products (for running under rocprofv3)")
+    ap.add_argument("--working", choices=["bf16", "fp16"], default=None,
+                    help="time the product in this low working precision (X, Y, operands in W; fp32 sums)")
     ap.add_argument("--kernel-hash", action="store_true",
                     help="print the source hash of each product path and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -400,6 +510,8 @@ def main():
     acc = h.info()["acc_dtype"]
     log(f"[bench] operator on GPU in {time.time() - t:.1f}s; formats {fmts}; acc {acc}")
 
+    if args.working:
+        return main_lowp(args, torch, H, cfg, h, op, fmts, nrhs0)
     xdt = torch.float32 if cfg.x_dtype == "fp32" else torch.float64
     xb = 4 if cfg.x_dtype == "fp32" else 8
     nrhs_list = [nrhs0] if args.profile_run else [nrhs0] + [k for k in cfg.nrhs if k != nrhs0]

@@ -81,7 +81,10 @@ struct LeafDesc {
     int32_t m;            // real rows
     int32_t mp;           // padded rows (= ld of D_i)
     int32_t prow0;        // padded row start
-    int32_t pad_;
+    int32_t kp;           // low working precision: columns of the ancestors' U in the augmented
+                          // operand (sum over levels of rank rounded up to 8, then up to 32)
+    int64_t aug_off;      // low working precision: element offset of the leaf's augmented operand
+                          // [D_i 0 | U_1 | ... | U_depth] (mp rows, row-major, ld = round_up(mp, 32) + kp)
 };
 
 struct CItem {            // contraction work item: rows [r0, r0+nr) of a V panel
@@ -108,7 +111,7 @@ struct KParams {
     const CItem* citems;
     const ETile* etiles;
     const double* tscale;
-    const void* leafw;           // low working precision: the leaves rounded to W, row-major (ld = mp)
+    const void* aug;             // low working precision: the augmented operands in W (LeafDesc::aug_off)
     void* Tw;                    // low working precision: T_b in W (sum of round_up(rank, 32) * nrhs)
     double* partial;             // workspace: sum over items of rank * nrhs
     double* T;                   // workspace: sum over blocks of rank * nrhs
@@ -129,6 +132,7 @@ struct KParams {
     int32_t max_tstage;          // matrix-core expansion: largest sum, over one leaf's ancestor
                                  // blocks, of round_up(rank, 4) * (8 if fp64 else 4) bytes
                                  // (T of every level staged in LDS, per LDS row element)
+    int32_t max_kp;              // low working precision: largest LeafDesc::kp
 };
 
 // Counters of the contraction launch: kSyncHead reserved words, then one
@@ -152,6 +156,9 @@ int launch_matvec(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_
 
 // low working precision (w = 0: bf16, 1: fp16): X and Y in W, every operand
 // rounded to W, fp32 accumulation on the matrix cores
+// build the augmented operands (LeafDesc::aug_off) of kp.aug in W (w = 0: bf16, 1: fp16)
+int launch_build_aug(const KParams& kp, int w, void* stream);
+
 int launch_matvec_lp(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs, int w,
                      void* stream, void* const* events, bool* ran);
 

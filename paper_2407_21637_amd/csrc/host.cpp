@@ -276,7 +276,10 @@ struct hodlr_op_s {
     int device = -1;
     uint8_t* d_fac = nullptr;
     double* d_leaf = nullptr;
-    void* d_leafw[2] = {nullptr, nullptr};     // the leaves rounded to bf16 / fp16, made on first use
+    void* d_aug[2] = {nullptr, nullptr};       // augmented operands in bf16 / fp16 (LeafDesc::aug_off)
+    uint64_t aug_gen[2] = {0, 0};              // pack generation each was built for (0: never)
+    int64_t aug_total = 0;                     // elements of one augmented image
+    int32_t max_kp = 0;
     BlockDesc* d_blocks = nullptr;
     LeafDesc* d_leaves = nullptr;
     CItem* d_citems = nullptr;
@@ -324,9 +327,10 @@ void free_device(hodlr_op_s* op) {
     free_profile(op);
     dev_free(op->d_fac);
     dev_free(op->d_leaf);
-    dev_free(op->d_leafw[0]);
-    dev_free(op->d_leafw[1]);
-    op->d_leafw[0] = op->d_leafw[1] = nullptr;
+    dev_free(op->d_aug[0]);
+    dev_free(op->d_aug[1]);
+    op->d_aug[0] = op->d_aug[1] = nullptr;
+    op->aug_gen[0] = op->aug_gen[1] = 0;
     dev_free(op->d_blocks);
     dev_free(op->d_leaves);
     dev_free(op->d_citems);
@@ -630,7 +634,8 @@ hodlr_status pack_leaves(hodlr_op_s* op) {
         return fail(HODLR_E_UNSUPPORTED, "padded size %lld exceeds 2^31 rows", (long long)pr);
     op->ldesc.assign(nl, LeafDesc{});
     op->etiles.clear();
-    int64_t doff = 0;
+    int64_t doff = 0, aug = 0;
+    op->max_kp = 0;
     for (int i = 0; i < nl; ++i) {
         LeafDesc& L = op->ldesc[i];
         L.d_off = doff;
@@ -639,6 +644,13 @@ hodlr_status pack_leaves(hodlr_op_s* op) {
         L.mp = int32_t(op->lmp[i]);
         L.prow0 = int32_t(op->lprow0[i]);
         doff += int64_t(L.mp) * L.mp;
+        // low working precision: the ancestors' ranks, each rounded up to 8, then the sum up to 32
+        int32_t kpl = 0;
+        for (int k = 1; k <= op->depth; ++k) kpl += (op->rank[size_t(((1 << k) - 2) + (i >> (op->depth - k)))] + 7) / 8 * 8;
+        L.kp = (kpl + 31) / 32 * 32;
+        L.aug_off = aug;
+        aug += int64_t(L.mp) * ((L.mp + 31) / 32 * 32 + L.kp);
+        op->max_kp = std::max(op->max_kp, L.kp);
         for (int32_t r = 0; r < L.mp; r += kTileRows) {
             ETile t{};
             t.leaf = i;
@@ -647,6 +659,7 @@ hodlr_status pack_leaves(hodlr_op_s* op) {
             op->etiles.push_back(t);
         }
     }
+    op->aug_total = aug;
     if (op->device < 0) return HODLR_OK;
     std::vector<double> img;
     try {
@@ -1036,16 +1049,25 @@ hodlr_status hodlr_export_block(hodlr_op op, int32_t block, void* u_codes, int8_
 
 namespace {
 
-// The leaves rounded (nearest even) to the working precision w (HODLR_BF16
-// or HODLR_FP16), row-major per leaf (ld = mp, zero padding), uploaded on
-// first use.  For fp16 every leaf entry and every factor value stored in a
-// format wider than fp16's range (fp64, fp32, bf16) must be finite in fp16
-// (E_RANGE otherwise); the narrow stored formats are scaled into range.
-hodlr_status ensure_leaves_w(hodlr_op_s* op, int32_t w) {
+// The augmented operands [D_i | U of the ancestors] in the working
+// precision w (HODLR_BF16 or HODLR_FP16), built on `stream` by the device
+// from the current image when it is older than the last pack.  For fp16
+// every leaf entry and every generator stored in a format wider than
+// fp16's range (fp64, fp32, bf16) must be finite in fp16 (E_RANGE
+// otherwise); the narrow stored formats are column-scaled into range.
+hodlr_status ensure_aug(hodlr_op_s* op, int32_t w, const KParams& kp, void* stream) {
     const int slot = w == HODLR_BF16 ? 0 : 1;
-    if (op->d_leafw[slot]) return HODLR_OK;
-    const int f = w == HODLR_BF16 ? BF16 : F16;
-    if (f == F16) {
+    if (op->d_aug[slot] && op->aug_gen[slot] == op->gen) return HODLR_OK;
+    if (w == HODLR_FP16) {
+        std::atomic<int> bad{-1};
+        parallel_for(op->nleaves, [&](int64_t i) {
+            for (double v : op->D[size_t(i)]) {
+                bool ovf = false;
+                (void)encode_rne(v, F16, &ovf);
+                if (ovf) { bad.store(int(i)); return; }
+            }
+        });
+        if (bad.load() >= 0) return fail(HODLR_E_RANGE, "leaf %d has an entry outside the fp16 range", bad.load());
         for (int b = 0; b < op->nb; ++b) {
             const int32_t bf = op->bdesc[size_t(b)].fmt;
             if (bf != F64 && bf != F32 && bf != BF16) continue;
@@ -1057,33 +1079,19 @@ hodlr_status ensure_leaves_w(hodlr_op_s* op, int32_t w) {
                 }
         }
     }
-    int64_t total = 0;
-    for (const LeafDesc& L : op->ldesc) total += int64_t(L.mp) * L.mp;
-    std::vector<uint16_t> img;
-    try {
-        img.assign(size_t(std::max<int64_t>(total, 1)), 0);
-    } catch (const std::bad_alloc&) {
-        return fail(HODLR_E_NOMEM, "host staging of the leaves in the working precision");
+    if (!op->d_aug[slot]) {
+        hipError_t e = hipMalloc(&op->d_aug[slot], size_t(std::max<int64_t>(op->aug_total, 1)) * 2);
+        if (e != hipSuccess) {
+            op->d_aug[slot] = nullptr;
+            (void)hipGetLastError();
+            return fail(HODLR_E_NOMEM, "augmented operand (%lld values)", (long long)op->aug_total);
+        }
     }
-    std::atomic<int> bad{-1};
-    parallel_for(op->nleaves, [&](int64_t i) {
-        const LeafDesc& L = op->ldesc[size_t(i)];
-        uint16_t* out = img.data() + L.d_off;
-        for (int64_t r = 0; r < L.m; ++r)
-            for (int64_t c = 0; c < L.m; ++c) {
-                bool ovf = false;
-                out[r * L.mp + c] = uint16_t(encode_rne(op->D[size_t(i)][size_t(c * L.m + r)], f, &ovf));
-                if (ovf) bad.store(int(i));
-            }
-    });
-    if (bad.load() >= 0)
-        return fail(HODLR_E_RANGE, "leaf %d has an entry outside the range of the working precision", bad.load());
-    hipError_t e = hipSetDevice(op->device);
-    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    uint16_t* d = nullptr;
-    hodlr_status r = upload(&d, img.data(), img.size(), "leaves in the working precision");
-    if (r != HODLR_OK) return r;
-    op->d_leafw[slot] = d;
+    KParams k2 = kp;
+    k2.aug = op->d_aug[slot];
+    const int he = launch_build_aug(k2, slot, stream);
+    if (he != 0) return fail(HODLR_E_DEVICE, "augmented operand: %s", hipGetErrorString(hipError_t(he)));
+    op->aug_gen[slot] = op->gen;
     return HODLR_OK;
 }
 
@@ -1151,6 +1159,7 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, int xy_by
     kp->max_leaf = op->max_leaf;
     kp->max_rank_path = op->max_rank_path;
     kp->max_tstage = op->max_tstage;
+    kp->max_kp = op->max_kp;
     kp->max_block_rank = op->max_block_rank;
     kp->max_items_rank = op->max_items_rank;
     kp->depth = op->depth;
@@ -1517,11 +1526,12 @@ hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int6
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     KParams kp{};
     const int xy_bytes = xy_dtype == HODLR_FP64 ? 8 : xy_dtype == HODLR_FP32 ? 4 : 2;
-    hodlr_status r;
-    if (lowp && (r = ensure_leaves_w(op, xy_dtype)) != HODLR_OK) return r;
-    r = prepare_workspace(op, stream, nrhs, xy_bytes, &kp);
+    hodlr_status r = prepare_workspace(op, stream, nrhs, xy_bytes, &kp);
     if (r != HODLR_OK) return r;
-    if (lowp) kp.leafw = op->d_leafw[xy_dtype == HODLR_BF16 ? 0 : 1];
+    if (lowp) {
+        if ((r = ensure_aug(op, xy_dtype, kp, stream)) != HODLR_OK) return r;
+        kp.aug = op->d_aug[xy_dtype == HODLR_BF16 ? 0 : 1];
+    }
     void* const* ev = nullptr;
     bool ran[kPhases] = {false, false, false, false};
     int32_t slot = -1;

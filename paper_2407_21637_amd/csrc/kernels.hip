@@ -211,6 +211,11 @@ int launch_matvec_lp(const KParams& kp, const void* X, int64_t ldx, void* Y, int
     return int(e);
 }
 
+int launch_build_aug(const KParams& kp, int w, void* stream) {
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    return int(w == 0 ? launch_build_aug_w<__bf16>(kp, s) : launch_build_aug_w<_Float16>(kp, s));
+}
+
 int plan_launch(const KParams& kp, const void* X, int64_t ldx, int nrhs, bool xy_double, bool acc_double,
                 OpLaunch* out) {
     OpLaunch o{};

@@ -8,8 +8,9 @@
 // Included by kernels.hip only.
 //
 // Rounding points (each round-to-nearest-even into W):
-//   * the leaf blocks, once per operator (a W copy next to the fp64 one);
-//   * each stored code value of U_b and V_b, in registers when loaded;
+//   * the leaf blocks and each stored code value of U_b, once per precision
+//     assignment (the augmented operand, k_build_aug);
+//   * each stored code value of V_b, in registers when loaded;
 //   * T_b = tscale * (V_b^T X) after its fp32 sum (stored in W);
 //   * Y once, after the fp32 sum of the leaf and all levels.
 // X arrives in W.
@@ -70,8 +71,8 @@ __device__ __forceinline__ typename LpMfma<W>::v8 codes_to_w8(const uint8_t* p) 
 // one MFMA covers the step.  PG rank tiles of 16 per pass; the waves'
 // blocks are added in LDS and stored as the item's fp64 partial ([j][c]).
 template <int F, typename W, int NT>
-__device__ void contract_item_lp(const KParams& kp, const CItem& it, const BlockDesc& bd, const W* __restrict__ X,
-                                 int64_t ldx, int nrhs, int c0, float* red) {
+__device__ void contract_item_lp(const KParams& kp, const CItem& it, const BlockDesc& bd, const W* __restrict__ X8,
+                                 int nrhs, int c0, float* red) {
     typedef LpMfma<W> M;
     typedef typename M::v8 V8;
     constexpr int S = Codec<F>::kBytes;
@@ -82,7 +83,7 @@ __device__ void contract_item_lp(const KParams& kp, const CItem& it, const Block
     const uint8_t* Vp = kp.fac + bd.v_off + int64_t(it.r0) * p * S;
     const int64_t ld = it.nr;
     double* part = kp.partial + it.poff * nrhs;
-    const W* Xr = X + int64_t(bd.vrow0) + it.r0;
+    const int64_t prow0 = int64_t(bd.vrow0) + it.r0;  // padded row of the item's first row
     const int nstep = (it.nr + kStep - 1) / kStep;
     const V8 zero = {};
     for (int j0 = 0; j0 < p; j0 += 16 * PG) {
@@ -103,7 +104,7 @@ __device__ void contract_item_lp(const KParams& kp, const CItem& it, const Block
 #pragma unroll
             for (int ct = 0; ct < NT; ++ct) {
                 const int c = c0 + 16 * ct + li;
-                b[ct] = (ok && c < nrhs) ? load_w8<W>(Xr + row + ldx * c) : zero;
+                b[ct] = (ok && c < nrhs) ? load_w8<W>(X8 + (((prow0 + row) >> 3) * nrhs + c) * 8) : zero;
             }
 #pragma unroll
             for (int pg = 0; pg < PG; ++pg)
@@ -134,20 +135,19 @@ __device__ void contract_item_lp(const KParams& kp, const CItem& it, const Block
 }
 
 template <typename W, int NT>
-__global__ __launch_bounds__(kThreads) void k_contract_lp(KParams kp, const W* __restrict__ X, int64_t ldx,
-                                                          int nrhs) {
+__global__ __launch_bounds__(kThreads) void k_contract_lp(KParams kp, const W* __restrict__ X8, int nrhs) {
     extern __shared__ double smem_d[];
     const CItem it = kp.citems[blockIdx.x];
     const BlockDesc bd = kp.blocks[it.block];
     const int c0 = blockIdx.y * 16 * NT;
     float* red = reinterpret_cast<float*>(smem_d);
     switch (bd.fmt) {
-        case F64: contract_item_lp<F64, W, NT>(kp, it, bd, X, ldx, nrhs, c0, red); break;
-        case F32: contract_item_lp<F32, W, NT>(kp, it, bd, X, ldx, nrhs, c0, red); break;
-        case BF16: contract_item_lp<BF16, W, NT>(kp, it, bd, X, ldx, nrhs, c0, red); break;
-        case F16: contract_item_lp<F16, W, NT>(kp, it, bd, X, ldx, nrhs, c0, red); break;
-        case E4M3: contract_item_lp<E4M3, W, NT>(kp, it, bd, X, ldx, nrhs, c0, red); break;
-        default: contract_item_lp<E5M2, W, NT>(kp, it, bd, X, ldx, nrhs, c0, red); break;
+        case F64: contract_item_lp<F64, W, NT>(kp, it, bd, X8, nrhs, c0, red); break;
+        case F32: contract_item_lp<F32, W, NT>(kp, it, bd, X8, nrhs, c0, red); break;
+        case BF16: contract_item_lp<BF16, W, NT>(kp, it, bd, X8, nrhs, c0, red); break;
+        case F16: contract_item_lp<F16, W, NT>(kp, it, bd, X8, nrhs, c0, red); break;
+        case E4M3: contract_item_lp<E4M3, W, NT>(kp, it, bd, X8, nrhs, c0, red); break;
+        default: contract_item_lp<E5M2, W, NT>(kp, it, bd, X8, nrhs, c0, red); break;
     }
 }
 
@@ -170,133 +170,255 @@ __global__ __launch_bounds__(256) void k_reduce_lp(KParams kp, int nrhs) {
     const double* src = kp.partial + kp.citems[bd.item0].poff * nrhs + int64_t(j) * nrhs + c;
     const int total = p * nrhs;
     float s = 0.0f;
-    for (int i = 0; i < bd.nitems; ++i) s += float(src[int64_t(i) * total]);
+    int i = 0;
+    for (; i + 8 <= bd.nitems; i += 8) {         // eight loads in flight, summed in item order
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = src[int64_t(i + q) * total];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s += float(v[q]);
+    }
+    for (; i < bd.nitems; ++i) s += float(src[int64_t(i) * total]);
     Tw[o] = W(double(s) * kp.tscale[bd.ts_off + j]);     // the scale is a power of two: one rounding
 }
 
 // ---------------------------------------------------------------------------
-// expansion: leaf GEMM and U_b T_b on the matrix cores, Y written once
+// the augmented operand: [D_i | U_1 | ... | U_depth] per leaf, in W
 // ---------------------------------------------------------------------------
-// One workgroup per (128-row tile, 16 NT right-hand sides); wave w owns
-// tile rows 32w..32w+31 as two 16-row MFMA tiles (h).  The K index of the
-// leaf GEMM (leaf columns) and of the low-rank products (ranks) runs in
-// steps of 32: lane group g holds K = 8g..8g+7 of a step for both operands.
-// The leaf's W copy is row-major (ld = mp), so a lane's eight K values are
-// one 16-byte load; X (column-major) likewise; T_b in W is [c][j].
-template <int F, typename W, int NT>
-__device__ void expand_level_lp(const KParams& kp, const BlockDesc& bd, int chunk0, int ld, int c0, int nrhs,
-                                int wave, int li, int g, f32x4 acc[2][NT]) {
-    typedef LpMfma<W> M;
-    typedef typename M::v8 V8;
-    constexpr int S = Codec<F>::kBytes;
-    const int p = bd.rank;
-    const int P = (p + 31) & ~31;
-    const uint8_t* Up = kp.fac + bd.u_off + int64_t(chunk0) * p * S;   // the tile's chunk: (j, row) at (j ld + row) S
-    const W* Tw = static_cast<const W*>(kp.Tw) + bd.tw_off * nrhs;
-    const V8 zero = {};
-    for (int j0 = 0; j0 < P; j0 += kStep) {
-        const int jg = j0 + kKL * g;                    // the lane's eight ranks
-        V8 a[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = 32 * wave + 16 * h + li;      // tile row
-            a[h] = zero;
-            if (r < ld) {
-#pragma unroll
-                for (int q = 0; q < kKL; ++q) {
-                    CodeT<F> v = 0;
-                    if (jg + q < p) Codec<F>::template load<1, CodeT<F>>(Up + (int64_t(jg + q) * ld + r) * S, &v);
-                    a[h][q] = W(v);
+// Row r of leaf i's operand holds D_i's row r (mp columns, then zeros up to
+// mp32 = round_up(mp, 32)), then for each level k the leaf's rows of the
+// ancestor block's U panel (rank p_k codes, rounded to W, then zeros up to
+// round_up(p_k, 8)), then zeros up to kp columns.  The expansion of a tile
+// is then one GEMM over K = mp32 + kp
+// against [X_i ; T_1 ; ... ; T_depth].  Built on the device from the packed
+// codes, once per precision assignment; fp64 values (the leaves, fp64
+// generators) are rounded to W directly, narrower codes through their
+// exact fp32 value.
+__device__ __forceinline__ int lp_code_bytes(int f) { return f == F64 ? 8 : f == F32 ? 4 : (f == BF16 || f == F16) ? 2 : 1; }
+
+template <typename W>
+__global__ __launch_bounds__(256) void k_build_aug(KParams kp) {
+    const ETile t = kp.etiles[blockIdx.x];
+    const LeafDesc L = kp.leaves[t.leaf];
+    const int depth = kp.depth;
+    const int mp32 = (L.mp + 31) & ~31;
+    const int ld = mp32 + L.kp;
+    W* A = static_cast<W*>(const_cast<void*>(kp.aug)) + L.aug_off + int64_t(t.r0) * ld;
+    const double* Dt = kp.leafd + L.d_off + int64_t(t.r0) * L.mp;      // tile: column-major, ld = nr
+    for (int64_t idx = threadIdx.x; idx < int64_t(t.nr) * ld; idx += 256) {
+        const int r = int(idx / ld), c = int(idx - (idx / ld) * ld);
+        W v = W(0.0f);
+        if (c < L.mp) {
+            v = W(Dt[int64_t(c) * t.nr + r]);
+        } else if (c >= mp32) {
+            int kk = c - mp32;
+            for (int k = 1; k <= depth; ++k) {
+                const BlockDesc bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
+                const int seg = (bd.rank + 7) & ~7;
+                if (kk < seg) {
+                    if (kk < bd.rank) {
+                        const int S = lp_code_bytes(bd.fmt);
+                        const int chunk0 = L.prow0 - bd.urow0 + t.r0;
+                        const uint8_t* q = kp.fac + bd.u_off + (int64_t(chunk0) * bd.rank + int64_t(kk) * t.nr + r) * S;
+                        switch (bd.fmt) {
+                            case F64: { double d; Codec<F64>::template load<1, double>(q, &d); v = W(d); } break;
+                            case F32: { float f; Codec<F32>::template load<1, float>(q, &f); v = W(f); } break;
+                            case BF16: { float f; Codec<BF16>::template load<1, float>(q, &f); v = W(f); } break;
+                            case F16: { float f; Codec<F16>::template load<1, float>(q, &f); v = W(f); } break;
+                            case E4M3: { float f; Codec<E4M3>::template load<1, float>(q, &f); v = W(f); } break;
+                            default: { float f; Codec<E5M2>::template load<1, float>(q, &f); v = W(f); } break;
+                        }
+                    }
+                    break;
                 }
+                kk -= seg;
             }
         }
+        A[int64_t(r) * ld + c] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// expansion: one GEMM per tile over the augmented operand, Y written once
+// ---------------------------------------------------------------------------
+// One workgroup per (128-row tile, 16 NT right-hand sides); wave w owns
+// tile rows 32w..32w+31 as two 16-row MFMA tiles (h).  K runs in steps of
+// 32: lane group g holds K = 8g..8g+7 of a step for both operands (one
+// 16-byte load each: the operand is row-major, X and the staged T are
+// column-major).  K < mp32 (mp rounded up to 32; the operand is zero in
+// [mp, mp32)) multiplies X_i from memory; the rest the ancestors' T_b,
+// staged at the start as an LDS copy [column][kp] in the operand's segment
+// order.  The leaf steps rotate through kLU register buffers: each is
+// refilled with the step kLU ahead as soon as its MFMAs are issued, so kLU
+// steps of loads stay in flight and no loaded value is tested.
+constexpr int kLU = 4;
+
+template <typename W, int NT>
+struct LpStep {                                  // the lane's operands of one step
+    typedef typename LpMfma<W>::v8 V8;
+    V8 a[2];
+    V8 b[NT];
+};
+
+// step `st` of the leaf part (steps past nsteps read column 0: never used)
+template <typename W, int NT>
+__device__ __forceinline__ void lp_load(LpStep<W, NT>& o, const W* A0, const W* A1, const W* X8, int prow0,
+                                        int st, int nsteps, int mp, int c0, int li, int g, int nrhs) {
+    const int k = st < nsteps ? kStep * st + kKL * g : 0;
+    o.a[0] = load_w8<W>(A0 + k);
+    o.a[1] = load_w8<W>(A1 + k);
+    const int kx = k < mp ? k : 0;               // rows of X past the leaf meet zero columns
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
-            const int c = c0 + 16 * ct + li;
-            const V8 b = c < nrhs ? load_w8<W>(Tw + int64_t(c) * P + jg) : zero;
-            acc[0][ct] = M::mma(a[0], b, acc[0][ct]);
-            acc[1][ct] = M::mma(a[1], b, acc[1][ct]);
-        }
+    for (int ct = 0; ct < NT; ++ct) {
+        const int c = c0 + 16 * ct + li;
+        o.b[ct] = load_w8<W>(X8 + (int64_t((prow0 + kx) >> 3) * nrhs + (c < nrhs ? c : c0)) * 8);
     }
 }
 
 template <typename W, int NT>
-__global__ __launch_bounds__(kThreads) void k_expand_lp(KParams kp, const W* __restrict__ Xw, int64_t ldw,
-                                                        W* __restrict__ Y, int64_t ldy, int nrhs) {
+__device__ __forceinline__ void lp_mma(const LpStep<W, NT>& o, f32x4 acc[2][NT]) {
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) {
+        acc[0][ct] = LpMfma<W>::mma(o.a[0], o.b[ct], acc[0][ct]);
+        acc[1][ct] = LpMfma<W>::mma(o.a[1], o.b[ct], acc[1][ct]);
+    }
+}
+
+template <typename W, int NT>
+__global__ __launch_bounds__(kThreads) void k_expand_lp(KParams kp, const W* __restrict__ X8, W* __restrict__ Y,
+                                                        int64_t ldy, int nrhs) {
     typedef LpMfma<W> M;
     typedef typename M::v8 V8;
+    constexpr int CW = 16 * NT;
+    extern __shared__ double smem_d[];
+    __shared__ int seg_k[kMaxDepth + 1];         // first operand column of each level's segment
+    __shared__ int seg_p[kMaxDepth];             // each level's rank
+    __shared__ int64_t seg_t[kMaxDepth];         // each level's T_b in W: element offset of column 0
+    W* ts = reinterpret_cast<W*>(smem_d);        // staged T: [column][kp]
     const ETile t = kp.etiles[blockIdx.x];
     const LeafDesc L = kp.leaves[t.leaf];
-    const int c0 = blockIdx.y * 16 * NT;
+    const int c0 = blockIdx.y * CW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, g = lane >> 4;
     const int depth = kp.depth;
+    const int mp32 = (L.mp + 31) & ~31;
+    const int ld = mp32 + L.kp;
+    const int nsteps = mp32 / kStep;
+    // rows past the tile read tile row li instead (present: nr >= 16); their results are not written
+    const W* A0 = static_cast<const W*>(kp.aug) + L.aug_off +
+                  int64_t(t.r0 + (32 * wave + li < t.nr ? 32 * wave + li : li)) * ld;
+    const W* A1 = static_cast<const W*>(kp.aug) + L.aug_off +
+                  int64_t(t.r0 + (32 * wave + 16 + li < t.nr ? 32 * wave + 16 + li : li)) * ld;
+    // the leaf's first kLU steps are fetched before the T staging
+    LpStep<W, NT> ring[kLU];
+#pragma unroll
+    for (int u = 0; u < kLU; ++u) lp_load<W, NT>(ring[u], A0, A1, X8, L.prow0, u, nsteps, L.mp, c0, li, g, nrhs);
+    if (threadIdx.x < depth) {                   // the ancestors' ranks and T_b offsets
+        const int k = threadIdx.x + 1;
+        const BlockDesc& bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
+        seg_p[k - 1] = bd.rank;
+        seg_t[k - 1] = bd.tw_off * nrhs + int64_t(c0) * ((bd.rank + 31) & ~31);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int off = 0;
+        for (int k = 1; k <= depth; ++k) {
+            seg_k[k - 1] = off;
+            off += (seg_p[k - 1] + 7) & ~7;
+        }
+        seg_k[depth] = off;
+    }
+    __syncthreads();
+    // stage T_b of the leaf's ancestors: ts[c][seg_k + j] = T_b[c0 + c][j], zero past the rank / nrhs / kp;
+    // each thread issues a batch of loads before it stores any
+    {
+        constexpr int kB = 8;
+        const W* Tw = static_cast<const W*>(kp.Tw);
+        const int tot = CW * L.kp;
+        for (int base = 0; base < tot; base += kB * kThreads) {
+            W v[kB];
+#pragma unroll
+            for (int i = 0; i < kB; ++i) {
+                const int idx = base + i * kThreads + int(threadIdx.x);
+                v[i] = W(0.0f);
+                if (idx < tot) {
+                    const int c = idx / L.kp, kk = idx - c * L.kp;
+                    if (kk < seg_k[depth] && c0 + c < nrhs) {
+                        int k = 1;
+                        while (k < depth && kk >= seg_k[k]) ++k;
+                        const int j = kk - seg_k[k - 1];
+                        const int p = seg_p[k - 1];
+                        if (j < p) v[i] = Tw[seg_t[k - 1] + int64_t(c) * ((p + 31) & ~31) + j];
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kB; ++i) {
+                const int idx = base + i * kThreads + int(threadIdx.x);
+                if (idx < tot) ts[idx] = v[i];
+            }
+        }
+    }
     f32x4 acc[2][NT];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < NT; ++b) zero_acc(acc[a][b]);
-    // leaf: rows of the tile (row-major W copy, ld = mp) times X_i
-    {
-        const W* Dw = static_cast<const W*>(kp.leafw) + L.d_off;
-        const W* Xl = Xw + L.prow0;
-        const V8 zero = {};
-        // rows past the tile read tile row li instead (present: nr >= 16); their results are not written
-        const int ra = t.r0 + (32 * wave + li < t.nr ? 32 * wave + li : li);
-        const int rb = t.r0 + (32 * wave + 16 + li < t.nr ? 32 * wave + 16 + li : li);
-        for (int k0 = 0; k0 < L.mp; k0 += kStep) {
-            const int k = k0 + kKL * g;
-            const bool ok = k < L.mp;                   // mp is a multiple of 16, k of 8
-            const int kk = ok ? k : 0;
-            const V8 a0 = load_w8<W>(Dw + int64_t(ra) * L.mp + kk);
-            const V8 a1 = load_w8<W>(Dw + int64_t(rb) * L.mp + kk);
+    // leaf: K in [0, mp32), X from memory
+    for (int s0 = 0; s0 < nsteps; s0 += kLU) {
 #pragma unroll
-            for (int ct = 0; ct < NT; ++ct) {
-                const int c = c0 + 16 * ct + li;
-                const V8 b = (ok && c < nrhs) ? load_w8<W>(Xl + kk + ldw * c) : zero;
-                acc[0][ct] = M::mma(a0, b, acc[0][ct]);
-                acc[1][ct] = M::mma(a1, b, acc[1][ct]);
-            }
+        for (int u = 0; u < kLU; ++u) {
+            if (s0 + u < nsteps) lp_mma<W, NT>(ring[u], acc);
+            lp_load<W, NT>(ring[u], A0, A1, X8, L.prow0, s0 + u + kLU, nsteps, L.mp, c0, li, g, nrhs);
         }
     }
-    // the depth ancestors' blocks whose rows contain this leaf
-    for (int k = 1; k <= depth; ++k) {
-        const BlockDesc bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
-        if (bd.rank == 0) continue;
-        const int chunk0 = L.prow0 - bd.urow0 + t.r0;
-        switch (bd.fmt) {
-            case F64: expand_level_lp<F64, W, NT>(kp, bd, chunk0, t.nr, c0, nrhs, wave, li, g, acc); break;
-            case F32: expand_level_lp<F32, W, NT>(kp, bd, chunk0, t.nr, c0, nrhs, wave, li, g, acc); break;
-            case BF16: expand_level_lp<BF16, W, NT>(kp, bd, chunk0, t.nr, c0, nrhs, wave, li, g, acc); break;
-            case F16: expand_level_lp<F16, W, NT>(kp, bd, chunk0, t.nr, c0, nrhs, wave, li, g, acc); break;
-            case E4M3: expand_level_lp<E4M3, W, NT>(kp, bd, chunk0, t.nr, c0, nrhs, wave, li, g, acc); break;
-            default: expand_level_lp<E5M2, W, NT>(kp, bd, chunk0, t.nr, c0, nrhs, wave, li, g, acc); break;
+    __syncthreads();                             // the staged T is complete
+    // low rank: K in [mp32, mp32 + kp), the staged T from LDS
+    for (int kk = 0; kk < L.kp; kk += kStep) {
+        const int j = kk + kKL * g;              // kp is a multiple of 32
+        const V8 a0 = load_w8<W>(A0 + mp32 + j);
+        const V8 a1 = load_w8<W>(A1 + mp32 + j);
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+            const V8 b = *reinterpret_cast<const V8*>(ts + (16 * ct + li) * L.kp + j);
+            acc[0][ct] = M::mma(a0, b, acc[0][ct]);
+            acc[1][ct] = M::mma(a1, b, acc[1][ct]);
         }
     }
-    // result element e of lane (li, g): tile row 16h + 4g + e of the wave, column li
+    // result element e of lane (li, g): tile row 16h + 4g + e of the wave,
+    // column li -- four consecutive rows of one column, written as one
+    // 8-byte store when they lie inside the leaf and are 8-byte aligned
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) {
             const int c = c0 + 16 * ct + li;
             if (c >= nrhs) continue;
+            const int rr = 32 * wave + 16 * h + 4 * g;
+            const int pr = t.r0 + rr;
+            W* dst = Y + L.row0 + pr + ldy * c;
+            if (rr + 3 < t.nr && pr + 3 < L.m && (reinterpret_cast<uintptr_t>(dst) & 7) == 0) {
+                typedef W w4 __attribute__((ext_vector_type(4)));
+                w4 v;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int rr = 32 * wave + 16 * h + 4 * g + e;
-                const int pr = t.r0 + rr;
-                if (rr < t.nr && pr < L.m) Y[L.row0 + pr + ldy * c] = W(acc[h][ct][e]);
+                for (int e = 0; e < 4; ++e) v[e] = W(acc[h][ct][e]);
+                *reinterpret_cast<w4*>(dst) = v;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (rr + e < t.nr && pr + e < L.m) dst[e] = W(acc[h][ct][e]);
             }
         }
 }
 
 template <typename W, int NT>
-hipError_t launch_lp_nt(const KParams& kp, const W* Xw, int64_t ldw, W* Y, int64_t ldy, int nrhs, const Timer& tm) {
+hipError_t launch_lp_nt(const KParams& kp, const W* X8, W* Y, int64_t ldy, int nrhs, const Timer& tm) {
     hipStream_t s = tm.s;
     const int gy = (nrhs + 16 * NT - 1) / (16 * NT);
     if (kp.ncitems > 0) {
         tm.begin(1);
         hipLaunchKernelGGL((k_contract_lp<W, NT>), dim3(kp.ncitems, gy), dim3(kThreads),
-                           size_t(kWaves) * NT * 256 * sizeof(float), s, kp, Xw, ldw, nrhs);
+                           size_t(kWaves) * NT * 256 * sizeof(float), s, kp, X8, nrhs);
         tm.end(1);
         tm.begin(3);
         const int64_t rows_y = (int64_t((kp.max_block_rank + 31) & ~31) * nrhs + 255) / 256;
@@ -304,9 +426,41 @@ hipError_t launch_lp_nt(const KParams& kp, const W* Xw, int64_t ldw, W* Y, int64
         tm.end(3);
     }
     tm.begin(2);
-    hipLaunchKernelGGL((k_expand_lp<W, NT>), dim3(kp.netiles, gy), dim3(kThreads), 0, s, kp, Xw, ldw, Y, ldy, nrhs);
+    hipLaunchKernelGGL((k_expand_lp<W, NT>), dim3(kp.netiles, gy), dim3(kThreads),
+                       size_t(std::max(kp.max_kp, 1)) * 16 * NT * sizeof(W), s, kp, X8, Y, ldy, nrhs);
     tm.end(2);
     return hipGetLastError();
+}
+
+// X in the 8-row blocked layout of the W path: padded row r, column c at
+// ((r / 8) nrhs + c) 8 + r mod 8, zero on padding rows, so that a lane's
+// 8 consecutive rows of one column and the 16 columns of a lane group are
+// one contiguous 256-byte run (the caller's column-major X, columns apart
+// by ldx, made every load instruction touch 16 distant columns)
+template <typename W>
+__global__ __launch_bounds__(256) void k_x8(KParams kp, const W* __restrict__ X, int64_t ldx, int nrhs) {
+    const LeafDesc L = kp.leaves[blockIdx.x];
+    W* X8 = static_cast<W*>(kp.xpad);
+    const int ng = L.mp >> 3;                           // 8-row groups of the leaf
+    typedef W w8 __attribute__((ext_vector_type(8)));
+    // units of 8 groups x 8 columns, one per 64 threads: lane l takes group
+    // l % 8 and column l / 8, so the reads are 128-byte runs of one column
+    // and the writes 128-byte runs of one group
+    const int ug = (ng + 7) >> 3, uc = (nrhs + 7) >> 3;
+    const int lane = threadIdx.x & 63;
+    for (int u = threadIdx.x >> 6; u < ug * uc; u += 4) {
+        const int grp = 8 * (u % ug) + (lane & 7), c = 8 * (u / ug) + (lane >> 3);
+        if (grp >= ng || c >= nrhs) continue;
+        const W* src = X + L.row0 + 8 * grp + ldx * c;
+        w8 v;
+        if (8 * grp + 7 < L.m && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+            v = *reinterpret_cast<const w8*>(src);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = 8 * grp + q < L.m ? src[q] : W(0.0f);
+        }
+        *reinterpret_cast<w8*>(X8 + ((int64_t(L.prow0 >> 3) + grp) * nrhs + c) * 8) = v;
+    }
 }
 
 template <typename W>
@@ -314,20 +468,23 @@ hipError_t launch_lp(const KParams& kp, const void* Xv, int64_t ldx, void* Yv, i
                      const Timer& tm) {
     const W* X = static_cast<const W*>(Xv);
     W* Y = static_cast<W*>(Yv);
-    // 16-byte loads of X need 16-byte aligned columns; padded leaves need the padded copy
-    const bool aligned = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((ldx * int64_t(sizeof(W))) % 16 == 0);
-    const W* Xw = X;
-    int64_t ldw = ldx;
-    if (kp.padded || !aligned) {
-        tm.begin(0);
-        hipLaunchKernelGGL((k_padx<W>), dim3(kp.nleaves), dim3(256), 0, tm.s, kp, X, ldx, nrhs);
-        tm.end(0);
-        Xw = static_cast<const W*>(kp.xpad);
-        ldw = kp.npad;
-    }
-    if (nrhs <= 16) return launch_lp_nt<W, 1>(kp, Xw, ldw, Y, ldy, nrhs, tm);
-    if (nrhs <= 32) return launch_lp_nt<W, 2>(kp, Xw, ldw, Y, ldy, nrhs, tm);
-    return launch_lp_nt<W, 4>(kp, Xw, ldw, Y, ldy, nrhs, tm);
+    tm.begin(0);
+    hipLaunchKernelGGL((k_x8<W>), dim3(kp.nleaves), dim3(256), 0, tm.s, kp, X, ldx, nrhs);
+    tm.end(0);
+    const W* X8 = static_cast<const W*>(kp.xpad);
+    // the staged T takes max_kp x 16 NT values of LDS
+    auto fits = [&](int nt) { return int64_t(kp.max_kp) * 16 * nt * int64_t(sizeof(W)) <= int64_t(kMaxLds); };
+    if (nrhs > 32 && fits(4)) return launch_lp_nt<W, 4>(kp, X8, Y, ldy, nrhs, tm);
+    if (nrhs > 16 && fits(2)) return launch_lp_nt<W, 2>(kp, X8, Y, ldy, nrhs, tm);
+    if (fits(1)) return launch_lp_nt<W, 1>(kp, X8, Y, ldy, nrhs, tm);
+    return hipErrorInvalidConfiguration;
+}
+
+// the augmented operand of every tile (k_build_aug)
+template <typename W>
+hipError_t launch_build_aug_w(const KParams& kp, hipStream_t s) {
+    hipLaunchKernelGGL((k_build_aug<W>), dim3(kp.netiles), dim3(256), 0, s, kp);
+    return hipGetLastError();
 }
 
 }  // namespace
