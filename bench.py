@@ -48,7 +48,8 @@ CSRC = os.path.join(ROOT, "paper_2407_21637_amd", "csrc")
 # device sources of each product path: a counter summary under profiles/
 # holds only while the hash of its path's sources is unchanged
 PATH_SOURCES = {"wave": ("hodlr_internal.h", "dev_common.h", "wave_path.h"),
-                "wide": ("hodlr_internal.h", "dev_common.h", "wave_path.h", "wide_path.h")}
+                "wide": ("hodlr_internal.h", "dev_common.h", "wave_path.h", "wide_path.h"),
+                "lowp": ("hodlr_internal.h", "dev_common.h", "wave_path.h", "wide_path.h", "lowp_path.h")}
 
 
 def log(*a):
@@ -259,7 +260,11 @@ def main_lowp(args, torch, H, cfg, h, op, fmts, nrhs):
     else:
         roof = {"bound": "hbm", "achieved": round(exp_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(exp_gbs / HBM_PEAK_GBS, 4)}
-    roof.update({"kernel": f"k_expand_lp ({w} MFMA leaf GEMM + low-rank, writes Y)", "traffic": None,
+    tr = read_traffic(f"{cfg.name}_{w}", nrhs)
+    traffic = None
+    if tr.get("kernel_sha") == kernel_hash("lowp") and tr.get("nrhs") == str(nrhs):
+        traffic = int(tr.get("second_launch_bytes", 0)) or None
+    roof.update({"kernel": f"k_expand_lp ({w} MFMA leaf GEMM + low-rank, writes Y)", "traffic": traffic,
                  "alg_bytes_per_launch": int(EB), "intensity_flop_per_byte": round(intensity, 2),
                  "mfma_tflops": round(LF / (exp_us * 1e-6) / 1e12, 2), "mean_launch_us": round(exp_us, 2)})
     value = B / (ms * 1e-3) / 1e9

@@ -295,9 +295,17 @@ __global__ __launch_bounds__(kThreads) void k_expand_lp(KParams kp, const W* __r
     __shared__ int seg_p[kMaxDepth];             // each level's rank
     __shared__ int64_t seg_t[kMaxDepth];         // each level's T_b in W: element offset of column 0
     W* ts = reinterpret_cast<W*>(smem_d);        // staged T: [column][kp]
-    const ETile t = kp.etiles[blockIdx.x];
+    // Each XCD (blocks b with the same b mod 8) takes a contiguous run of
+    // (tile, column group) units, column groups innermost: the column groups
+    // and the tiles of a leaf run back to back on one XCD, so the operand
+    // rows and X rows they share are read from that XCD's L2.
+    const int ncg = (nrhs + CW - 1) / CW;
+    const int units = kp.netiles * ncg, per = (units + 7) / 8;
+    const int u = int(blockIdx.x & 7) * per + int(blockIdx.x >> 3);
+    if (u >= units) return;                      // whole block: before any barrier
+    const ETile t = kp.etiles[u / ncg];
     const LeafDesc L = kp.leaves[t.leaf];
-    const int c0 = blockIdx.y * CW;
+    const int c0 = (u % ncg) * CW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, g = lane >> 4;
     const int depth = kp.depth;
@@ -426,7 +434,7 @@ hipError_t launch_lp_nt(const KParams& kp, const W* X8, W* Y, int64_t ldy, int n
         tm.end(3);
     }
     tm.begin(2);
-    hipLaunchKernelGGL((k_expand_lp<W, NT>), dim3(kp.netiles, gy), dim3(kThreads),
+    hipLaunchKernelGGL((k_expand_lp<W, NT>), dim3(8 * ((kp.netiles * gy + 7) / 8)), dim3(kThreads),
                        size_t(std::max(kp.max_kp, 1)) * 16 * NT * sizeof(W), s, kp, X8, Y, ldy, nrhs);
     tm.end(2);
     return hipGetLastError();
