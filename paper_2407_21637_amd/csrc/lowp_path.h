@@ -248,9 +248,12 @@ __global__ __launch_bounds__(256) void k_build_aug(KParams kp) {
 // column-major).  K < mp32 (mp rounded up to 32; the operand is zero in
 // [mp, mp32)) multiplies X_i from memory; the rest the ancestors' T_b,
 // staged at the start as an LDS copy [column][kp] in the operand's segment
-// order.  The leaf steps rotate through kLU register buffers: each is
-// refilled with the step kLU ahead as soon as its MFMAs are issued, so kLU
-// steps of loads stay in flight and no loaded value is tested.
+// order.  The steps rotate through kLU register buffers: each is refilled
+// with the step kLU ahead as soon as its MFMAs are issued, so kLU steps of
+// operand loads stay in flight and no loaded value is tested.  The step
+// numbering puts the low-rank steps at nsr = round_up(nsteps, kLU), so
+// the leaf loop already fetches the first low-rank operands into the
+// buffers the low-rank loop reads first (steps in [nsteps, nsr) do nothing).
 constexpr int kLU = 4;
 
 template <typename W, int NT>
@@ -260,14 +263,21 @@ struct LpStep {                                  // the lane's operands of one s
     V8 b[NT];
 };
 
-// step `st` of the leaf part (steps past nsteps read column 0: never used)
+// operand column of lane group g at step st (see above; steps outside both parts read column 0)
+__device__ __forceinline__ int lp_col(int st, int nsteps, int nsr, int ntot, int g) {
+    return st < nsteps ? kStep * st + kKL * g : (st >= nsr && st < ntot) ? kStep * (st - nsr + nsteps) + kKL * g : 0;
+}
+
+// step st of the leaf loop: the operand and, for a leaf step, X's rows (the X
+// part of any other step reads row 0 and is never used)
 template <typename W, int NT>
 __device__ __forceinline__ void lp_load(LpStep<W, NT>& o, const W* A0, const W* A1, const W* X8, int prow0,
-                                        int st, int nsteps, int mp, int c0, int li, int g, int nrhs) {
-    const int k = st < nsteps ? kStep * st + kKL * g : 0;
+                                        int st, int nsteps, int nsr, int ntot, int mp, int c0, int li, int g,
+                                        int nrhs) {
+    const int k = lp_col(st, nsteps, nsr, ntot, g);
     o.a[0] = load_w8<W>(A0 + k);
     o.a[1] = load_w8<W>(A1 + k);
-    const int kx = k < mp ? k : 0;               // rows of X past the leaf meet zero columns
+    const int kx = st < nsteps && k < mp ? k : 0;     // rows of X past the leaf meet zero columns
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) {
         const int c = c0 + 16 * ct + li;
@@ -312,6 +322,8 @@ __global__ __launch_bounds__(kThreads) void k_expand_lp(KParams kp, const W* __r
     const int mp32 = (L.mp + 31) & ~31;
     const int ld = mp32 + L.kp;
     const int nsteps = mp32 / kStep;
+    const int nsr = (nsteps + kLU - 1) / kLU * kLU;
+    const int ntot = nsr + L.kp / kStep;         // kp is a multiple of 32
     // rows past the tile read tile row li instead (present: nr >= 16); their results are not written
     const W* A0 = static_cast<const W*>(kp.aug) + L.aug_off +
                   int64_t(t.r0 + (32 * wave + li < t.nr ? 32 * wave + li : li)) * ld;
@@ -320,7 +332,8 @@ __global__ __launch_bounds__(kThreads) void k_expand_lp(KParams kp, const W* __r
     // the leaf's first kLU steps are fetched before the T staging
     LpStep<W, NT> ring[kLU];
 #pragma unroll
-    for (int u = 0; u < kLU; ++u) lp_load<W, NT>(ring[u], A0, A1, X8, L.prow0, u, nsteps, L.mp, c0, li, g, nrhs);
+    for (int u = 0; u < kLU; ++u)
+        lp_load<W, NT>(ring[u], A0, A1, X8, L.prow0, u, nsteps, nsr, ntot, L.mp, c0, li, g, nrhs);
     if (threadIdx.x < depth) {                   // the ancestors' ranks and T_b offsets
         const int k = threadIdx.x + 1;
         const BlockDesc& bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
@@ -337,60 +350,71 @@ __global__ __launch_bounds__(kThreads) void k_expand_lp(KParams kp, const W* __r
         seg_k[depth] = off;
     }
     __syncthreads();
-    // stage T_b of the leaf's ancestors: ts[c][seg_k + j] = T_b[c0 + c][j], zero past the rank / nrhs / kp;
-    // each thread issues a batch of loads before it stores any
+    // stage T_b of the leaf's ancestors: ts[c][seg_k + j] = T_b[c0 + c][j], zero past the rank / nrhs / kp,
+    // in 16-byte chunks (a segment is round_up(p, 8) wide and T_b is stored zero from p up to a multiple
+    // of 32, so a chunk never crosses a column); each thread issues its loads before it stores any
     {
-        constexpr int kB = 8;
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        constexpr int kB = 4;
         const W* Tw = static_cast<const W*>(kp.Tw);
-        const int tot = CW * L.kp;
+        const int kc = L.kp / 8;                 // chunks per staged column
+        const int tot = CW * kc;
         for (int base = 0; base < tot; base += kB * kThreads) {
-            W v[kB];
+            u32x4 v[kB];
 #pragma unroll
             for (int i = 0; i < kB; ++i) {
                 const int idx = base + i * kThreads + int(threadIdx.x);
-                v[i] = W(0.0f);
+                v[i] = u32x4{0u, 0u, 0u, 0u};
                 if (idx < tot) {
-                    const int c = idx / L.kp, kk = idx - c * L.kp;
+                    const int c = idx / kc, kk = (idx - c * kc) * 8;
                     if (kk < seg_k[depth] && c0 + c < nrhs) {
                         int k = 1;
                         while (k < depth && kk >= seg_k[k]) ++k;
                         const int j = kk - seg_k[k - 1];
                         const int p = seg_p[k - 1];
-                        if (j < p) v[i] = Tw[seg_t[k - 1] + int64_t(c) * ((p + 31) & ~31) + j];
+                        if (j < p)
+                            v[i] = *reinterpret_cast<const u32x4*>(Tw + seg_t[k - 1] + int64_t(c) * ((p + 31) & ~31) + j);
                     }
                 }
             }
 #pragma unroll
             for (int i = 0; i < kB; ++i) {
                 const int idx = base + i * kThreads + int(threadIdx.x);
-                if (idx < tot) ts[idx] = v[i];
+                if (idx < tot) *reinterpret_cast<u32x4*>(ts + idx * 8) = v[i];
             }
         }
     }
+    __syncthreads();                             // the staged T is complete
     f32x4 acc[2][NT];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < NT; ++b) zero_acc(acc[a][b]);
     // leaf: K in [0, mp32), X from memory
-    for (int s0 = 0; s0 < nsteps; s0 += kLU) {
+    for (int s0 = 0; s0 < nsr; s0 += kLU) {
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
             if (s0 + u < nsteps) lp_mma<W, NT>(ring[u], acc);
-            lp_load<W, NT>(ring[u], A0, A1, X8, L.prow0, s0 + u + kLU, nsteps, L.mp, c0, li, g, nrhs);
+            lp_load<W, NT>(ring[u], A0, A1, X8, L.prow0, s0 + u + kLU, nsteps, nsr, ntot, L.mp, c0, li, g, nrhs);
         }
     }
-    __syncthreads();                             // the staged T is complete
-    // low rank: K in [mp32, mp32 + kp), the staged T from LDS
-    for (int kk = 0; kk < L.kp; kk += kStep) {
-        const int j = kk + kKL * g;              // kp is a multiple of 32
-        const V8 a0 = load_w8<W>(A0 + mp32 + j);
-        const V8 a1 = load_w8<W>(A1 + mp32 + j);
+    // low rank: K in [mp32, mp32 + kp), the staged T from LDS; only the operand part of the buffers is refilled
+    for (int s0 = nsr; s0 < ntot; s0 += kLU) {
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
-            const V8 b = *reinterpret_cast<const V8*>(ts + (16 * ct + li) * L.kp + j);
-            acc[0][ct] = M::mma(a0, b, acc[0][ct]);
-            acc[1][ct] = M::mma(a1, b, acc[1][ct]);
+        for (int u = 0; u < kLU; ++u) {
+            const int st = s0 + u;
+            if (st < ntot) {
+                const int j = (st - nsr) * kStep + kKL * g;
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct) {
+                    const V8 b = *reinterpret_cast<const V8*>(ts + (16 * ct + li) * L.kp + j);
+                    acc[0][ct] = M::mma(ring[u].a[0], b, acc[0][ct]);
+                    acc[1][ct] = M::mma(ring[u].a[1], b, acc[1][ct]);
+                }
+            }
+            const int k = lp_col(st + kLU, nsteps, nsr, ntot, g);
+            ring[u].a[0] = load_w8<W>(A0 + k);
+            ring[u].a[1] = load_w8<W>(A1 + k);
         }
     }
     // result element e of lane (li, g): tile row 16h + 4g + e of the wave,
