@@ -475,23 +475,35 @@ __global__ __launch_bounds__(256) void k_x8(KParams kp, const W* __restrict__ X,
     W* X8 = static_cast<W*>(kp.xpad);
     const int ng = L.mp >> 3;                           // 8-row groups of the leaf
     typedef W w8 __attribute__((ext_vector_type(8)));
-    // units of 8 groups x 8 columns, one per 64 threads: lane l takes group
-    // l % 8 and column l / 8, so the reads are 128-byte runs of one column
-    // and the writes 128-byte runs of one group
-    const int ug = (ng + 7) >> 3, uc = (nrhs + 7) >> 3;
-    const int lane = threadIdx.x & 63;
-    for (int u = threadIdx.x >> 6; u < ug * uc; u += 4) {
-        const int grp = 8 * (u % ug) + (lane & 7), c = 8 * (u / ug) + (lane >> 3);
-        if (grp >= ng || c >= nrhs) continue;
-        const W* src = X + L.row0 + 8 * grp + ldx * c;
-        w8 v;
-        if (8 * grp + 7 < L.m && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
-            v = *reinterpret_cast<const w8*>(src);
-        } else {
+    // units of 8 groups x 8 columns, one per wave: lane l takes group l % 8
+    // and column l / 8, so the reads are 128-byte runs of one column and the
+    // writes 128-byte runs of one group.  Blocks (leaf, y) take runs of 16
+    // units (4 per wave, their loads issued before any store), strided by
+    // gridDim.y
+    constexpr int kU = 4;
+    const int ug = (ng + 7) >> 3, uc = (nrhs + 7) >> 3, nu = ug * uc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int ub = int(blockIdx.y) * 4 * kU; ub < nu; ub += int(gridDim.y) * 4 * kU) {
+        w8 v[kU];
+        int64_t dst[kU];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = 8 * grp + q < L.m ? src[q] : W(0.0f);
+        for (int i = 0; i < kU; ++i) {
+            const int u = ub + wave * kU + i;
+            const int grp = 8 * (u % ug) + (lane & 7), c = 8 * (u / ug) + (lane >> 3);
+            dst[i] = -1;
+            if (u >= nu || grp >= ng || c >= nrhs) continue;
+            const W* src = X + L.row0 + 8 * grp + ldx * c;
+            if (8 * grp + 7 < L.m && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+                v[i] = *reinterpret_cast<const w8*>(src);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[i][q] = 8 * grp + q < L.m ? src[q] : W(0.0f);
+            }
+            dst[i] = ((int64_t(L.prow0 >> 3) + grp) * nrhs + c) * 8;
         }
-        *reinterpret_cast<w8*>(X8 + ((int64_t(L.prow0 >> 3) + grp) * nrhs + c) * 8) = v;
+#pragma unroll
+        for (int i = 0; i < kU; ++i)
+            if (dst[i] >= 0) *reinterpret_cast<w8*>(X8 + dst[i]) = v[i];
     }
 }
 
@@ -501,7 +513,12 @@ hipError_t launch_lp(const KParams& kp, const void* Xv, int64_t ldx, void* Yv, i
     const W* X = static_cast<const W*>(Xv);
     W* Y = static_cast<W*>(Yv);
     tm.begin(0);
-    hipLaunchKernelGGL((k_x8<W>), dim3(kp.nleaves), dim3(256), 0, tm.s, kp, X, ldx, nrhs);
+    {
+        // units of the largest leaf (mp <= max_leaf rounded up to 32), 16 per block
+        const int64_t nu = int64_t((((kp.max_leaf + 31) & ~31) / 8 + 7) / 8) * ((nrhs + 7) / 8);
+        const unsigned gy = unsigned(std::min<int64_t>((nu + 15) / 16, 4096));
+        hipLaunchKernelGGL((k_x8<W>), dim3(kp.nleaves, std::max(gy, 1u)), dim3(256), 0, tm.s, kp, X, ldx, nrhs);
+    }
     tm.end(0);
     const W* X8 = static_cast<const W*>(kp.xpad);
     // the staged T takes max_kp x 16 NT values of LDS
