@@ -243,12 +243,14 @@ __global__ __launch_bounds__(256) void k_build_aug(KParams kp) {
 // ---------------------------------------------------------------------------
 // One workgroup per (128-row tile, 16 NT right-hand sides); wave w owns
 // tile rows 32w..32w+31 as two 16-row MFMA tiles (h).  K runs in steps of
-// 32: lane group g holds K = 8g..8g+7 of a step for both operands (one
-// 16-byte load each: the operand is row-major, X and the staged T are
+// 32: lane group g holds K = 8g..8g+7 of a step for both operands (16
+// bytes each: the operand is row-major, X and the staged T are
 // column-major).  K < mp32 (mp rounded up to 32; the operand is zero in
-// [mp, mp32)) multiplies X_i from memory; the rest the ancestors' T_b,
-// staged at the start as an LDS copy [column][kp] in the operand's segment
-// order.  The steps rotate through kLU register buffers: each is refilled
+// [mp, mp32)) multiplies X_i: the workgroup loads a step's 32 x 16 NT
+// block of X once (thread t one 16-byte piece) into one of kLU LDS
+// buffers, and every wave reads it from there after a barrier.  The rest
+// of K multiplies the ancestors' T_b, staged at the start as an LDS copy
+// [column][kp] in the operand's segment order.  The steps rotate through kLU register buffers: each is refilled
 // with the step kLU ahead as soon as its MFMAs are issued, so kLU steps of
 // operand loads stay in flight and no loaded value is tested.  The step
 // numbering puts the low-rank steps at nsr = round_up(nsteps, kLU), so
@@ -260,7 +262,7 @@ template <typename W, int NT>
 struct LpStep {                                  // the lane's operands of one step
     typedef typename LpMfma<W>::v8 V8;
     V8 a[2];
-    V8 b[NT];
+    V8 xq;                                       // the thread's piece of the step's X block
 };
 
 // operand column of lane group g at step st (see above; steps outside both parts read column 0)
@@ -268,29 +270,24 @@ __device__ __forceinline__ int lp_col(int st, int nsteps, int nsr, int ntot, int
     return st < nsteps ? kStep * st + kKL * g : (st >= nsr && st < ntot) ? kStep * (st - nsr + nsteps) + kKL * g : 0;
 }
 
-// step st of the leaf loop: the operand and, for a leaf step, X's rows (the X
-// part of any other step reads row 0 and is never used)
+// step st of the leaf loop: the operand and, for threads t < 64 NT (whole
+// waves), piece t of X's 32 x 16 NT block: rows 8 (t / 16 NT) .. + 7 of the
+// step, column c0 + t mod 16 NT (rows of any other step read row 0 and are
+// never used)
 template <typename W, int NT>
 __device__ __forceinline__ void lp_load(LpStep<W, NT>& o, const W* A0, const W* A1, const W* X8, int prow0,
-                                        int st, int nsteps, int nsr, int ntot, int mp, int c0, int li, int g,
+                                        int st, int nsteps, int nsr, int ntot, int mp, int c0, int g,
                                         int nrhs) {
+    constexpr int CW = 16 * NT;
     const int k = lp_col(st, nsteps, nsr, ntot, g);
     o.a[0] = load_w8<W>(A0 + k);
     o.a[1] = load_w8<W>(A1 + k);
-    const int kx = st < nsteps && k < mp ? k : 0;     // rows of X past the leaf meet zero columns
-#pragma unroll
-    for (int ct = 0; ct < NT; ++ct) {
-        const int c = c0 + 16 * ct + li;
-        o.b[ct] = load_w8<W>(X8 + (int64_t((prow0 + kx) >> 3) * nrhs + (c < nrhs ? c : c0)) * 8);
-    }
-}
-
-template <typename W, int NT>
-__device__ __forceinline__ void lp_mma(const LpStep<W, NT>& o, f32x4 acc[2][NT]) {
-#pragma unroll
-    for (int ct = 0; ct < NT; ++ct) {
-        acc[0][ct] = LpMfma<W>::mma(o.a[0], o.b[ct], acc[0][ct]);
-        acc[1][ct] = LpMfma<W>::mma(o.a[1], o.b[ct], acc[1][ct]);
+    const int t = int(threadIdx.x);
+    if (t < 4 * CW) {                            // uniform per wave
+        const int kq = kStep * st + kKL * (t / CW);
+        const int kx = st < nsteps && kq < mp ? kq : 0;    // rows of X past the leaf meet zero columns
+        const int c = c0 + t % CW;
+        o.xq = load_w8<W>(X8 + (int64_t((prow0 + kx) >> 3) * nrhs + (c < nrhs ? c : c0)) * 8);
     }
 }
 
@@ -305,6 +302,7 @@ __global__ __launch_bounds__(kThreads) void k_expand_lp(KParams kp, const W* __r
     __shared__ int seg_p[kMaxDepth];             // each level's rank
     __shared__ int64_t seg_t[kMaxDepth];         // each level's T_b in W: element offset of column 0
     W* ts = reinterpret_cast<W*>(smem_d);        // staged T: [column][kp]
+    W* xs = ts + int64_t(kp.max_kp) * CW;        // kLU X blocks of 4 CW pieces of 8 values
     // Each XCD (blocks b with the same b mod 8) takes a contiguous run of
     // (tile, column group) units, column groups innermost: the column groups
     // and the tiles of a leaf run back to back on one XCD, so the operand
@@ -333,7 +331,7 @@ __global__ __launch_bounds__(kThreads) void k_expand_lp(KParams kp, const W* __r
     LpStep<W, NT> ring[kLU];
 #pragma unroll
     for (int u = 0; u < kLU; ++u)
-        lp_load<W, NT>(ring[u], A0, A1, X8, L.prow0, u, nsteps, nsr, ntot, L.mp, c0, li, g, nrhs);
+        lp_load<W, NT>(ring[u], A0, A1, X8, L.prow0, u, nsteps, nsr, ntot, L.mp, c0, g, nrhs);
     if (threadIdx.x < depth) {                   // the ancestors' ranks and T_b offsets
         const int k = threadIdx.x + 1;
         const BlockDesc& bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
@@ -390,12 +388,24 @@ __global__ __launch_bounds__(kThreads) void k_expand_lp(KParams kp, const W* __r
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < NT; ++b) zero_acc(acc[a][b]);
-    // leaf: K in [0, mp32), X from memory
+    // leaf: K in [0, mp32), X through LDS buffer u.  Buffer u is rewritten at
+    // step st + kLU only after the barrier of step st + kLU - 1, which every
+    // wave reaches after its reads of step st.
     for (int s0 = 0; s0 < nsr; s0 += kLU) {
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
-            if (s0 + u < nsteps) lp_mma<W, NT>(ring[u], acc);
-            lp_load<W, NT>(ring[u], A0, A1, X8, L.prow0, s0 + u + kLU, nsteps, nsr, ntot, L.mp, c0, li, g, nrhs);
+            if (s0 + u < nsteps) {                   // uniform: the barrier is reached by every thread
+                W* xb = xs + u * (4 * CW * kKL);
+                if (int(threadIdx.x) < 4 * CW) *reinterpret_cast<V8*>(xb + threadIdx.x * kKL) = ring[u].xq;
+                __syncthreads();
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct) {
+                    const V8 b = *reinterpret_cast<const V8*>(xb + (g * CW + 16 * ct + li) * kKL);
+                    acc[0][ct] = M::mma(ring[u].a[0], b, acc[0][ct]);
+                    acc[1][ct] = M::mma(ring[u].a[1], b, acc[1][ct]);
+                }
+            }
+            lp_load<W, NT>(ring[u], A0, A1, X8, L.prow0, s0 + u + kLU, nsteps, nsr, ntot, L.mp, c0, g, nrhs);
         }
     }
     // low rank: K in [mp32, mp32 + kp), the staged T from LDS; only the operand part of the buffers is refilled
@@ -443,6 +453,13 @@ __global__ __launch_bounds__(kThreads) void k_expand_lp(KParams kp, const W* __r
         }
 }
 
+// dynamic LDS of k_expand_lp: the staged T (max_kp x 16 NT values) and kLU
+// X blocks (32 x 16 NT values each)
+template <typename W>
+size_t lp_expand_lds(const KParams& kp, int nt) {
+    return (size_t(kp.max_kp) * 16 * nt + size_t(kLU) * 32 * 16 * nt) * sizeof(W);
+}
+
 template <typename W, int NT>
 hipError_t launch_lp_nt(const KParams& kp, const W* X8, W* Y, int64_t ldy, int nrhs, const Timer& tm) {
     hipStream_t s = tm.s;
@@ -459,7 +476,7 @@ hipError_t launch_lp_nt(const KParams& kp, const W* X8, W* Y, int64_t ldy, int n
     }
     tm.begin(2);
     hipLaunchKernelGGL((k_expand_lp<W, NT>), dim3(8 * ((kp.netiles * gy + 7) / 8)), dim3(kThreads),
-                       size_t(std::max(kp.max_kp, 1)) * 16 * NT * sizeof(W), s, kp, X8, Y, ldy, nrhs);
+                       lp_expand_lds<W>(kp, NT), s, kp, X8, Y, ldy, nrhs);
     tm.end(2);
     return hipGetLastError();
 }
@@ -521,8 +538,7 @@ hipError_t launch_lp(const KParams& kp, const void* Xv, int64_t ldx, void* Yv, i
     }
     tm.end(0);
     const W* X8 = static_cast<const W*>(kp.xpad);
-    // the staged T takes max_kp x 16 NT values of LDS
-    auto fits = [&](int nt) { return int64_t(kp.max_kp) * 16 * nt * int64_t(sizeof(W)) <= int64_t(kMaxLds); };
+    auto fits = [&](int nt) { return int64_t(lp_expand_lds<W>(kp, nt)) <= int64_t(kMaxLds); };
     if (nrhs > 32 && fits(4)) return launch_lp_nt<W, 4>(kp, X8, Y, ldy, nrhs, tm);
     if (nrhs > 16 && fits(2)) return launch_lp_nt<W, 2>(kp, X8, Y, ldy, nrhs, tm);
     if (fits(1)) return launch_lp_nt<W, 1>(kp, X8, Y, ldy, nrhs, tm);
