@@ -92,25 +92,32 @@ __device__ void contract_item_lp(const KParams& kp, const CItem& it, const Block
         for (int a = 0; a < PG; ++a)
 #pragma unroll
             for (int b = 0; b < NT; ++b) zero_acc(acc[a][b]);
-        for (int st = wave; st < nstep; st += kWaves) {
-            const int row = st * kStep + g * kKL;       // nr and row are multiples of 8
-            const bool ok = row < it.nr;
-            V8 a[PG], b[NT];
+        // two of the wave's steps per pass, both loaded before either is multiplied (the
+        // accumulation order, step st then st + kWaves, is that of one step per pass)
+        for (int st = wave; st < nstep; st += 2 * kWaves) {
+            V8 a[2][PG], b[2][NT];
 #pragma unroll
-            for (int pg = 0; pg < PG; ++pg) {
-                const int j = j0 + 16 * pg + li;
-                a[pg] = (ok && j < p) ? codes_to_w8<F, W>(Vp + (int64_t(j) * ld + row) * S) : zero;
+            for (int h = 0; h < 2; ++h) {
+                const int row = (st + h * kWaves) * kStep + g * kKL;   // nr and row are multiples of 8
+                const bool ok = row < it.nr;
+#pragma unroll
+                for (int pg = 0; pg < PG; ++pg) {
+                    const int j = j0 + 16 * pg + li;
+                    a[h][pg] = (ok && j < p) ? codes_to_w8<F, W>(Vp + (int64_t(j) * ld + row) * S) : zero;
+                }
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct) {
+                    const int c = c0 + 16 * ct + li;
+                    b[h][ct] = (ok && c < nrhs) ? load_w8<W>(X8 + (((prow0 + row) >> 3) * nrhs + c) * 8) : zero;
+                }
             }
 #pragma unroll
-            for (int ct = 0; ct < NT; ++ct) {
-                const int c = c0 + 16 * ct + li;
-                b[ct] = (ok && c < nrhs) ? load_w8<W>(X8 + (((prow0 + row) >> 3) * nrhs + c) * 8) : zero;
-            }
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int pg = 0; pg < PG; ++pg)
-                if (j0 + 16 * pg < p)
+                for (int pg = 0; pg < PG; ++pg)
+                    if (j0 + 16 * pg < p)
 #pragma unroll
-                    for (int ct = 0; ct < NT; ++ct) acc[pg][ct] = M::mma(a[pg], b[ct], acc[pg][ct]);
+                        for (int ct = 0; ct < NT; ++ct) acc[pg][ct] = M::mma(a[h][pg], b[h][ct], acc[pg][ct]);
         }
         // add the four waves' blocks, one rank tile at a time
 #pragma unroll
