@@ -470,9 +470,9 @@ def main():
                     help="run a 256 MiB device-to-device copy 5 times (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the product shards by subtree with a "
-                                   "small exchange of T (see DESIGN.md), which is not implemented; "
-                                   "run with --gpus 1"}), flush=True)
+        print(json.dumps({"error": "the product runs on one GPU; a multi-GPU product would give each GPU "
+                                   "a subtree (its leaves and blocks) and exchange the top levels' small "
+                                   "T_b, which is not implemented; run with --gpus 1"}), flush=True)
         sys.exit(2)
     if args.kernel_hash:
         print(json.dumps({k: kernel_hash(k) for k in PATH_SOURCES}))
