@@ -51,7 +51,7 @@ typedef enum {
     HODLR_E_NOMEM = 3,        /* host or device allocation failed */
     HODLR_E_DEVICE = 4,       /* a HIP runtime call or a launch failed */
     HODLR_E_RANGE = 5,        /* a factor overflows its storage format (no column scaling) */
-    HODLR_E_UNSUPPORTED = 6   /* valid request this build does not support */
+    HODLR_E_UNSUPPORTED = 6   /* valid request the library does not support */
 } hodlr_status;
 
 /* Storage / arithmetic formats.  u = 2^-t: fp64 2^-53, fp32 2^-24, bf16 2^-8,
