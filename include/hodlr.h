@@ -13,7 +13,8 @@
  * Conventions shared by every entry point:
  *  - All functions return hodlr_status; no exception or abort crosses the
  *    ABI.  On error nothing is enqueued on any stream and the handle is
- *    unchanged; hodlr_last_error() gives a detail string (thread-local).
+ *    unchanged; hodlr_last_error_message() gives a detail string
+ *    (thread-local).
  *  - Matrices are column-major.  X and Y are n x nrhs with leading
  *    dimension ldx, ldy >= n; Y is overwritten (the algorithm starts from
  *    b = 0).  X and Y are device pointers owned by the caller and must stay
@@ -37,6 +38,8 @@
 #define HODLR_H
 
 #include <stdint.h>
+
+#include <hip/hip_runtime_api.h>   /* hipStream_t */
 
 #ifdef __cplusplus
 extern "C" {
@@ -142,10 +145,14 @@ hodlr_status hodlr_create(hodlr_op* out, int64_t n, int32_t depth, const int64_t
  * for each level k, xi_k = sqrt(nrm_k / nrmAll), u'_k = eps / (2^(k/2) xi_k)
  * (2^(k/2) evaluated as sqrt(2^k)), and u_k is the largest unit roundoff
  * <= u'_k among fp64 and `allowed` (n_allowed entries of hodlr_dtype).
- * norms2: NULL, or 1 + nblocks values: ||A||_F^2 followed by ||A_b||_F^2 of
- * the original blocks in canonical order (nrm_k is their maximum over level
- * k).  With NULL the norms are computed from the stored fp64 factors and
- * leaves (the H~ of Thm. 3.1).  If no format meets u'_k the level is fp64
+ * xi: NULL, or depth values xi_1..xi_depth (finite, >= 0) used as given,
+ * e.g. the algorithm's values computed elsewhere from the original matrix;
+ * the decisions then depend on nothing else.  Without xi they come from
+ * the norms.  norms2: NULL, or 1 + nblocks values: ||A||_F^2 followed by
+ * ||A_b||_F^2 of the original blocks in canonical order (nrm_k is their
+ * maximum over level k).  With NULL the norms are computed from the stored
+ * fp64 factors and leaves (the H~ of Thm. 3.1); they are not needed when
+ * xi is given without HODLR_PER_BLOCK.  If no format meets u'_k the level is fp64
  * and marked insufficient; if xi_k = 0 the coarsest allowed format is used.
  * Accumulation: fp64 if eps < 1e-7, else fp32, unless a HODLR_ACC_* flag
  * forces it.  The factors are then quantised (round to nearest even, once,
@@ -160,7 +167,8 @@ hodlr_status hodlr_create(hodlr_op* out, int64_t n, int32_t depth, const int64_t
  * each block's format.  hodlr_set_level_precisions returns to one format
  * per level. */
 hodlr_status hodlr_assign_precision(hodlr_op op, double eps, const int32_t* allowed,
-                                    int32_t n_allowed, const double* norms2, uint32_t flags);
+                                    int32_t n_allowed, const double* xi, const double* norms2,
+                                    uint32_t flags);
 
 /* Explicit per-level formats (Alg. "Mixed-precision HODLR Format"):
  * per_level[k-1] is level k's storage format.  Accumulation: fp64 when
@@ -174,6 +182,25 @@ hodlr_status hodlr_get_level(hodlr_op op, int32_t level, int32_t* dtype, double*
 
 hodlr_status hodlr_get_info(hodlr_op op, hodlr_info* info);
 hodlr_status hodlr_get_block(hodlr_op op, int32_t block, hodlr_block_info* info);
+
+/* Everything about an operator in one call: the hodlr_info fields, the
+ * last assignment of every level (format, xi_k, u'_k and the insufficient
+ * mark of Alg. "Adaptive-precision HODLR Format"; entries past depth are
+ * 0) and whether blocks carry their own formats (HODLR_PER_BLOCK).
+ * leaf_bounds: NULL, or room for 2^depth + 1 values (leaf node boundaries,
+ * Def. 2.1); ranks: NULL, or room for nblocks values (canonical order). */
+#define HODLR_MAX_LEVELS 24
+typedef struct {
+    hodlr_info info;
+    int32_t level_dtype[HODLR_MAX_LEVELS];
+    int32_t insufficient[HODLR_MAX_LEVELS];
+    double xi[HODLR_MAX_LEVELS];
+    double u_prime[HODLR_MAX_LEVELS];
+    int32_t per_block;
+    int32_t reserved_;
+} hodlr_query_info;
+
+hodlr_status hodlr_query(hodlr_op op, hodlr_query_info* q, int64_t* leaf_bounds, int32_t* ranks);
 
 /* Stored codes of block b: u_codes gets r_b x rank codes (column-major,
  * ld = r_b, element size s(f) bytes: the format's bit patterns), u_exp the
@@ -204,11 +231,19 @@ hodlr_status hodlr_export_block(hodlr_op op, int32_t block, void* u_codes, int8_
  * T_b or Y entry beyond the range becomes infinite.  Not available in
  * hodlr_matvec_batched.
  *
- * stream is a hipStream_t (NULL: the default stream).  The call only
- * enqueues work; on first use with a larger nrhs it may allocate (and
- * synchronise for) a bigger workspace. */
+ * stream: NULL is the default stream.  The call only enqueues work, except
+ * that the first call on a stream, or with a larger nrhs than before on
+ * it, allocates that stream's workspace (and the first bf16 / fp16 call
+ * after an assignment builds that format's operand and waits for it), so
+ * such a call must not be made while the stream is being captured
+ * (E_STATE for the operand; capture rules forbid the allocation).
+ *
+ * Graphs: the products may be captured into a HIP graph.  Such a graph
+ * stays valid until the handle is destroyed or reassigned (assign or
+ * set_level_precisions replace the device image it reads); workspaces that
+ * later calls outgrow are kept, not freed, until hodlr_destroy. */
 hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int64_t ldy,
-                          int32_t nrhs, int32_t xy_dtype, void* stream);
+                          int32_t nrhs, int32_t xy_dtype, hipStream_t stream);
 
 /* count independent products Y_i = A_i X_i (each as hodlr_matvec defines
  * it; the paper treats one operator at a time, this is the batch of many).
@@ -223,7 +258,8 @@ hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int6
  * The first call with a given signature (handles and their current images,
  * X/Y pointers, leading dimensions, nrhs, dtypes, stream) builds a plan:
  * it uploads the work lists (device memory held until a handle in it is
- * destroyed or 32 newer plans evict it), times the candidate launch shapes
+ * destroyed or, unless a caller's graph has recorded the plan's launches,
+ * 32 newer plans evict it), times the candidate launch shapes
  * on `stream` (work order longest-first or as given; 1, 2, 4 or 8
  * workgroups per compute unit; skipped when the environment sets
  * HODLR_BATCH_TUNE=0), keeps the fastest and captures the launches into a
@@ -234,7 +270,7 @@ hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int6
  * capture.  Argument errors are reported before anything is enqueued. */
 hodlr_status hodlr_matvec_batched(const hodlr_op* ops, int32_t count, const void* const* X,
                                   const int64_t* ldx, void* const* Y, const int64_t* ldy,
-                                  const int32_t* nrhs, const int32_t* xy_dtype, void* stream);
+                                  const int32_t* nrhs, const int32_t* xy_dtype, hipStream_t stream);
 
 /* Per-phase GPU timing.  capacity > 0 makes the next `capacity` products
  * of this handle record a HIP event pair around each of their kernel phases
@@ -253,7 +289,8 @@ hodlr_status hodlr_profile_read(hodlr_op op, double* ms_per_phase, int64_t* laun
 hodlr_status hodlr_destroy(hodlr_op op);
 
 const char* hodlr_status_string(hodlr_status s);
-const char* hodlr_last_error(void);
+const char* hodlr_last_error_message(void);   /* thread-local detail of the last failure */
+const char* hodlr_last_error(void);           /* the same string (earlier name) */
 
 #ifdef __cplusplus
 }

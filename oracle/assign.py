@@ -92,6 +92,23 @@ def assign(norm2_all: float, nrm_levels, eps: float, allowed,
     return Assignment(xis, ups, fmts, bad)
 
 
+def assign_from_xi(xi_levels, eps: float, allowed, working: str = "fp64") -> Assignment:
+    """The rule of Alg. "Adaptive-precision HODLR Format" from the point
+    where xi_k is known: u'_k = eps / (2^(k/2) xi_k) and the largest
+    candidate unit roundoff <= u'_k, for xi given per level (k = 1..depth)."""
+    cands = _candidates(allowed, working)
+    xis, ups, fmts, bad = [], [], [], []
+    for k, xi in enumerate(xi_levels, start=1):
+        xi = float(xi)
+        up = math.inf if xi == 0.0 else eps / (math.sqrt(float(2 ** k)) * xi)
+        ok = [c for c in cands if F.FORMATS[c].u <= up]
+        xis.append(xi)
+        ups.append(up)
+        fmts.append(max(ok, key=lambda nm: F.FORMATS[nm].u) if ok else "fp64")
+        bad.append(not ok)
+    return Assignment(xis, ups, fmts, bad)
+
+
 def assign_blocks(norm2_all: float, norm2_blocks, levels, eps: float, allowed,
                   working: str = "fp64") -> Assignment:
     """Per-block variant (module docstring): one entry per block, in the

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -30,9 +31,12 @@ STATUS = {0: "HODLR_OK", 1: "HODLR_E_ARG", 2: "HODLR_E_STATE", 3: "HODLR_E_NOMEM
 # every symbol include/hodlr.h declares
 EXPORTS = ("hodlr_depth_for_leaf", "hodlr_tree_bounds", "hodlr_tree_blocks", "hodlr_create",
            "hodlr_assign_precision", "hodlr_set_level_precisions", "hodlr_get_level",
-           "hodlr_get_info", "hodlr_get_block", "hodlr_export_block", "hodlr_matvec",
-           "hodlr_matvec_batched", "hodlr_profile", "hodlr_profile_read", "hodlr_destroy",
-           "hodlr_status_string", "hodlr_last_error")
+           "hodlr_get_info", "hodlr_get_block", "hodlr_query", "hodlr_export_block", "hodlr_matvec",
+           "hodlr_matvec_batched", "hodlr_profile", "hodlr_profile_read",
+           "hodlr_destroy", "hodlr_status_string", "hodlr_last_error_message", "hodlr_last_error")
+# entry points that return something other than hodlr_status
+_NON_STATUS = ("hodlr_depth_for_leaf", "hodlr_status_string", "hodlr_last_error_message", "hodlr_last_error")
+MAX_LEVELS = 24
 
 PHASES = ("pad_x", "contract", "expand", "reduce")
 
@@ -54,6 +58,12 @@ class Info(C.Structure):
                 ("device", C.c_int32), ("eps", C.c_double), ("leaf_bytes", C.c_int64),
                 ("factor_bytes", C.c_int64), ("scale_bytes", C.c_int64),
                 ("device_bytes", C.c_int64)]
+
+
+class QueryInfo(C.Structure):
+    _fields_ = [("info", Info), ("level_dtype", C.c_int32 * MAX_LEVELS), ("insufficient", C.c_int32 * MAX_LEVELS),
+                ("xi", C.c_double * MAX_LEVELS), ("u_prime", C.c_double * MAX_LEVELS),
+                ("per_block", C.c_int32), ("reserved_", C.c_int32)]
 
 
 class BlockInfo(C.Structure):
@@ -78,11 +88,12 @@ def lib():
         L.hodlr_tree_bounds.argtypes = [i64, i32, vp, vp]
         L.hodlr_tree_blocks.argtypes = [i64, i32, vp, vp]
         L.hodlr_create.argtypes = [C.POINTER(vp), i64, i32, vp, vp, vp, vp, i32]
-        L.hodlr_assign_precision.argtypes = [vp, dp, vp, i32, vp, C.c_uint32]
+        L.hodlr_assign_precision.argtypes = [vp, dp, vp, i32, vp, vp, C.c_uint32]
         L.hodlr_set_level_precisions.argtypes = [vp, vp, C.c_uint32]
         L.hodlr_get_level.argtypes = [vp, i32, vp, vp, vp, vp]
         L.hodlr_get_info.argtypes = [vp, vp]
         L.hodlr_get_block.argtypes = [vp, i32, vp]
+        L.hodlr_query.argtypes = [vp, vp, vp, vp]
         L.hodlr_export_block.argtypes = [vp, i32, vp, vp, vp, vp, i32]
         L.hodlr_matvec.argtypes = [vp, vp, i64, vp, i64, i32, i32, vp]
         L.hodlr_matvec_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
@@ -93,8 +104,10 @@ def lib():
         L.hodlr_status_string.restype = C.c_char_p
         L.hodlr_last_error.argtypes = []
         L.hodlr_last_error.restype = C.c_char_p
+        L.hodlr_last_error_message.argtypes = []
+        L.hodlr_last_error_message.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("hodlr_depth_for_leaf", "hodlr_status_string", "hodlr_last_error"):
+            if name not in _NON_STATUS:
                 getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -102,7 +115,7 @@ def lib():
 
 def _check(st):
     if st != 0:
-        raise HodlrError(st, lib().hodlr_last_error().decode())
+        raise HodlrError(st, lib().hodlr_last_error_message().decode())
 
 
 def _ptr(a):
@@ -189,19 +202,25 @@ class Operator:
         lb = None if leaf_bounds is None else np.ascontiguousarray(leaf_bounds, dtype=np.int64)
         _check(lib().hodlr_create(C.byref(self._h), n, depth, _ptr(lb),
                                   C.cast(lp, C.c_void_p), _ptr(ld), C.cast(blks, C.c_void_p), device))
-        self.n, self.depth, self.nblocks = n, depth, nb
+        self.n, self.depth, self.nblocks, self.device = n, depth, nb, device
 
     @property
     def handle(self):
         return self._h
 
-    def assign_precision(self, eps, allowed, norms2=None, flags=0):
+    def assign_precision(self, eps, allowed, norms2=None, flags=0, xi=None):
+        """Alg. "Adaptive-precision HODLR Format" (``hodlr_assign_precision``);
+        xi: optional per-level xi_1..xi_depth used as given."""
         al = np.array([DTYPES[a] if isinstance(a, str) else int(a) for a in allowed] or [0],
                       dtype=np.int32)
         nr = None if norms2 is None else np.ascontiguousarray(norms2, dtype=np.float64)
         if nr is not None and nr.size != 1 + self.nblocks:
             raise ValueError("norms2 needs 1 + nblocks values")
-        _check(lib().hodlr_assign_precision(self._h, float(eps), _ptr(al), len(allowed), _ptr(nr), flags))
+        xa = None if xi is None else np.ascontiguousarray(xi, dtype=np.float64)
+        if xa is not None and xa.size != self.depth:
+            raise ValueError("xi needs depth values")
+        _check(lib().hodlr_assign_precision(self._h, float(eps), _ptr(al), len(allowed), _ptr(xa), _ptr(nr),
+                                            flags))
 
     def set_level_precisions(self, per_level, flags=0):
         pl = np.array([DTYPES[a] if isinstance(a, str) else int(a) for a in per_level] or [0],
@@ -224,6 +243,23 @@ class Operator:
         d["acc_dtype"] = DTYPE_NAMES[d["acc_dtype"]]
         return d
 
+    def query(self):
+        """``hodlr_query``: info, per-level format / xi / u' / insufficient,
+        leaf bounds and ranks in one call."""
+        q = QueryInfo()
+        lb = np.zeros((1 << self.depth) + 1, dtype=np.int64)
+        rk = np.zeros(max(self.nblocks, 1), dtype=np.int32)
+        _check(lib().hodlr_query(self._h, C.byref(q), _ptr(lb), _ptr(rk)))
+        d = {f: getattr(q.info, f) for f, _ in Info._fields_}
+        d["acc_dtype"] = DTYPE_NAMES[d["acc_dtype"]]
+        L = self.depth
+        d["levels"] = [(DTYPE_NAMES[q.level_dtype[k]], q.xi[k], q.u_prime[k], bool(q.insufficient[k]))
+                       for k in range(L)]
+        d["per_block"] = bool(q.per_block)
+        d["leaf_bounds"] = lb
+        d["ranks"] = rk[:self.nblocks]
+        return d
+
     def block(self, b):
         bi = BlockInfo()
         _check(lib().hodlr_get_block(self._h, b, C.byref(bi)))
@@ -243,18 +279,12 @@ class Operator:
                                         1 if from_device else 0))
         return uc, ue[:p].astype(np.int64), vc, ve[:p].astype(np.int64)
 
-    def matvec(self, X, Y=None, stream=None):
-        """Y = A_H X for torch tensors on the operator's GPU; X is (n,) or
-        (n, nrhs) column-major.  float64 / float32 X: the product as
-        hodlr_matvec defines it for those dtypes; bfloat16 / float16 X: the
-        product in that low working precision.  Returns Y (allocated if None)."""
-        import torch
+    def _xy(self, X, Y):
+        """Checked (X pointer, ldx, Y, Y pointer, ldy, nrhs, dtype code)."""
+        code = _xy_code(X)
         xp, ldx, nrhs = _colmajor(X, self.n)
-        codes = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2, torch.float16: 3}
-        if X.dtype not in codes:
-            raise TypeError("X must be float64, float32, bfloat16 or float16")
-        code = codes[X.dtype]
         if Y is None:
+            import torch
             Y = torch.empty(self.n, dtype=X.dtype, device=X.device) if X.dim() == 1 else \
                 colmajor_empty(self.n, nrhs, X.dtype, X.device)
         if Y.dtype != X.dtype:
@@ -262,6 +292,16 @@ class Operator:
         yp, ldy, ny = _colmajor(Y, self.n)
         if ny != nrhs:
             raise ValueError("Y has a different nrhs")
+        _on_device(X, self.device, "X")
+        _on_device(Y, self.device, "Y")
+        return xp, ldx, Y, yp, ldy, nrhs, code
+
+    def matvec(self, X, Y=None, stream=None):
+        """Y = A_H X for torch tensors on the operator's GPU; X is (n,) or
+        (n, nrhs) column-major.  float64 / float32 X: the product as
+        hodlr_matvec defines it for those dtypes; bfloat16 / float16 X: the
+        product in that low working precision.  Returns Y (allocated if None)."""
+        xp, ldx, Y, yp, ldy, nrhs, code = self._xy(X, Y)
         _check(lib().hodlr_matvec(self._h, C.c_void_p(xp), ldx, C.c_void_p(yp), ldy, nrhs, code,
                                   _stream_ptr(stream)))
         return Y
@@ -283,16 +323,35 @@ class Operator:
             self._h = C.c_void_p()
 
     def __del__(self):
+        # during interpreter shutdown the HIP runtime may already be gone:
+        # leave the handle to the process exit instead of calling into it
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
             pass
 
 
+def _xy_code(X):
+    """hodlr_dtype code of a torch tensor's dtype (TypeError for any other)."""
+    import torch
+    codes = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2, torch.float16: 3}
+    if X.dtype not in codes:
+        raise TypeError("X must be float64, float32, bfloat16 or float16")
+    return codes[X.dtype]
+
+
+def _on_device(t, device, what):
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{what} must be on the operator's GPU (cuda:{device}), not {t.device}")
+
+
 def matvec_batched(ops, Xs, Ys, stream=None):
     """Y_i = A_i X_i for every operator, one call (``hodlr_matvec_batched``)."""
-    import torch
     k = len(ops)
+    if len(Xs) != k or len(Ys) != k:
+        raise ValueError("need one X and one Y per operator")
     hp = (C.c_void_p * k)(*[o.handle.value for o in ops])
     xp = (C.c_void_p * k)()
     yp = (C.c_void_p * k)()
@@ -301,10 +360,9 @@ def matvec_batched(ops, Xs, Ys, stream=None):
     nr = np.zeros(k, dtype=np.int32)
     dt = np.zeros(k, dtype=np.int32)
     for i, (o, X, Y) in enumerate(zip(ops, Xs, Ys)):
-        a, ldx[i], nr[i] = _colmajor(X, o.n)
-        b, ldy[i], _ = _colmajor(Y, o.n)
-        xp[i], yp[i] = a, b
-        dt[i] = 1 if X.dtype == torch.float32 else 0
+        if Y is None:
+            raise ValueError("matvec_batched needs every Y")
+        xp[i], ldx[i], _, yp[i], ldy[i], nr[i], dt[i] = o._xy(X, Y)
     _check(lib().hodlr_matvec_batched(C.cast(hp, C.c_void_p), k, C.cast(xp, C.c_void_p), _ptr(ldx),
                                       C.cast(yp, C.c_void_p), _ptr(ldy), _ptr(nr), _ptr(dt),
                                       _stream_ptr(stream)))

@@ -2,8 +2,8 @@
 
     python -m paper_2407_21637_amd.build        (or build() from Python)
 
-Compiles ``csrc/host.cpp`` (host core and C ABI) and ``csrc/kernels.hip``
-(device kernels) with hipcc and links them into
+Compiles ``csrc/host.cpp`` (host core and C ABI) and the device translation
+units ``csrc/kernels*.hip`` side by side with hipcc and links them into
 ``paper_2407_21637_amd/libhodlr.so``, and ``csrc/calibrate.hip`` (the
 machine-ceiling probe) into ``paper_2407_21637_amd/calibrate``.  Packed-fp32 instructions are turned
 off for the device code (``-packed-fp32-ops``), and MFMA accumulators are
@@ -46,25 +46,45 @@ def _run(cmd):
     return r.stdout
 
 
+def _run_all(cmds):
+    """Run independent compile steps side by side; raise on the first failure."""
+    procs = [(c, subprocess.Popen(c, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)) for c in cmds]
+    failed = None
+    for c, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0 and failed is None:
+            failed = (c, out)
+    if failed:
+        sys.stderr.write(" ".join(failed[0]) + "\n" + failed[1])
+        raise RuntimeError(f"build step failed: {failed[0][-1]}")
+
+
+# device translation units of the library (compiled in parallel)
+DEVICE_TUS = ("kernels.hip", "kernels_lowp.hip", "kernels_batch.hip")
+
+
 def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     with tempfile.TemporaryDirectory(prefix="hodlr_build_") as tmp:
         host_o = os.path.join(tmp, "host.o")
-        kern_o = os.path.join(tmp, "kernels.o")
-        _run([hipcc, "-std=c++17", "-O2", "-fPIC", "-Wall", "-c", *inc,
-              os.path.join(CSRC, "host.cpp"), "-o", host_o])
-        _run([hipcc, "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-c", *inc,
-              "-x", "hip", os.path.join(CSRC, "kernels.hip"), "-o", kern_o])
-        tmp_lib = os.path.join(tmp, "libhodlr.so")
-        _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", host_o, kern_o, "-o", tmp_lib,
-              "-lpthread"])
-        shutil.copyfile(tmp_lib, LIB + ".tmp")
-        os.replace(LIB + ".tmp", LIB)
+        objs = [host_o]
+        cmds = [[hipcc, "-std=c++17", "-O2", "-fPIC", "-Wall", "-c", *inc,
+                 os.path.join(CSRC, "host.cpp"), "-o", host_o]]
+        for tu in DEVICE_TUS:
+            o = os.path.join(tmp, tu.replace(".hip", ".o"))
+            objs.append(o)
+            cmds.append([hipcc, "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-c", *inc,
+                         "-x", "hip", os.path.join(CSRC, tu), "-o", o])
         # the machine-ceiling probe (a standalone program, not linked into the library)
         tmp_cal = os.path.join(tmp, "calibrate")
-        _run([hipcc, "-std=c++17", "-O3", f"--offload-arch={ARCH}", *DEVICE_FLAGS,
-              os.path.join(CSRC, "calibrate.hip"), "-o", tmp_cal])
+        cmds.append([hipcc, "-std=c++17", "-O3", f"--offload-arch={ARCH}", *DEVICE_FLAGS,
+                     os.path.join(CSRC, "calibrate.hip"), "-o", tmp_cal])
+        _run_all(cmds)
+        tmp_lib = os.path.join(tmp, "libhodlr.so")
+        _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp_lib, "-lpthread"])
+        shutil.copyfile(tmp_lib, LIB + ".tmp")
+        os.replace(LIB + ".tmp", LIB)
         shutil.copyfile(tmp_cal, CALIBRATE + ".tmp")
         os.chmod(CALIBRATE + ".tmp", 0o755)
         os.replace(CALIBRATE + ".tmp", CALIBRATE)

@@ -1,7 +1,8 @@
 // Machine ceilings of one gfx950 GPU, measured rather than taken from the
 // data sheet: the matrix-core rate of each MFMA the product kernels use
 // (register operands, no memory traffic, 1, 2 and 4 waves per SIMD) and
-// the HBM rate of a plain device-to-device copy.  A standalone program,
+// the HBM rate of a plain device-to-device copy and of a read-only stream
+// over a buffer much larger than the last-level cache.  A standalone program,
 // not part of the library; it prints one JSON object per measurement.
 //
 //   paper_2407_21637_amd/calibrate [scale]
@@ -87,6 +88,35 @@ __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ a, floa
     for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < n; i += size_t(gridDim.x) * 256) b[i] = a[i];
 }
 
+// Read-only stream: every lane issues U independent 16-byte loads per
+// step (grid-strided), sums them, and writes one value per workgroup at
+// the end, so the kernel's HBM traffic is the buffer read once.
+template <int U>
+__global__ __launch_bounds__(256) void k_read(const float4* __restrict__ a, size_t n, float* __restrict__ out) {
+    float acc = 0.0f;
+    const size_t stride = size_t(gridDim.x) * 256;
+    size_t i = blockIdx.x * size_t(256) + threadIdx.x;
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = a[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += v[u].x + v[u].y + v[u].z + v[u].w;
+    }
+    for (; i < n; i += stride) {
+        const float4 v = a[i];
+        acc += v.x + v.y + v.z + v.w;
+    }
+    __shared__ float red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.0f;
+        for (int t = 0; t < 256; ++t) s += red[t];
+        out[blockIdx.x] = s;
+    }
+}
+
 int compute_units() {
     hipDeviceProp_t p;
     CHECK(hipGetDeviceProperties(&p, 0));
@@ -160,6 +190,48 @@ void run_copy(int cus) {
     CHECK(hipFree(b));
 }
 
+template <int U>
+void run_read_one(const float4* a, size_t n, int blocks, float* out, size_t bytes) {
+    hipLaunchKernelGGL(k_read<U>, dim3(blocks), dim3(256), 0, 0, a, n, out);     // warm-up (TLB, clocks)
+    CHECK(hipGetLastError());
+    CHECK(hipDeviceSynchronize());
+    hipEvent_t e0, e1;
+    CHECK(hipEventCreate(&e0));
+    CHECK(hipEventCreate(&e1));
+    const int reps = 5;
+    CHECK(hipEventRecord(e0, 0));
+    for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(k_read<U>, dim3(blocks), dim3(256), 0, 0, a, n, out);
+    CHECK(hipGetLastError());
+    CHECK(hipEventRecord(e1, 0));
+    CHECK(hipEventSynchronize(e1));
+    float ms = 0;
+    CHECK(hipEventElapsedTime(&ms, e0, e1));
+    std::printf("{\"probe\": \"read\", \"bytes\": %zu, \"workgroups\": %d, \"loads_in_flight_per_lane\": %d, "
+                "\"ms_per_read\": %.4f, \"gbs\": %.1f}\n",
+                bytes, blocks, U, ms / reps, double(bytes) * reps / (ms * 1e-3) / 1e9);
+    std::fflush(stdout);
+    CHECK(hipEventDestroy(e0));
+    CHECK(hipEventDestroy(e1));
+}
+
+// A buffer 16x the 256 MB last-level cache, read once per launch: the
+// achievable HBM read rate (no reuse can hide in the cache).
+void run_read(int cus) {
+    const size_t bytes = size_t(4) << 30;
+    const size_t n = bytes / sizeof(float4);
+    float4* a;
+    float* out;
+    CHECK(hipMalloc(&a, bytes));
+    CHECK(hipMalloc(&out, sizeof(float) * 64 * size_t(cus)));
+    CHECK(hipMemset(a, 0, bytes));
+    for (int mult : {4, 8, 16, 32}) {
+        run_read_one<4>(a, n, cus * mult, out, bytes);
+        run_read_one<8>(a, n, cus * mult, out, bytes);
+    }
+    CHECK(hipFree(a));
+    CHECK(hipFree(out));
+}
+
 int main(int argc, char** argv) {
     const int scale = argc > 1 ? std::atoi(argv[1]) : 1;
     if (scale < 1 || scale > 1000) {
@@ -169,6 +241,7 @@ int main(int argc, char** argv) {
     const int cus = compute_units();
     std::printf("{\"probe\": \"device\", \"compute_units\": %d, \"scale\": %d}\n", cus, scale);
     run_copy(cus);
+    run_read(cus);
     sweep<kF64>(cus, 4000 * scale);
     sweep<kF32>(cus, 8000 * scale);
     sweep<kF16>(cus, 8000 * scale);

@@ -227,6 +227,9 @@ struct Workspace {
     int32_t* sync = nullptr;   // counters of the fused launch; zeroed once, self-resetting
     int64_t cap_partial = 0, cap_T = 0, cap_xpad = 0, cap_sync = 0, cap_W = 0, cap_Tw = 0;
     uint64_t gen = 0;          // bumped whenever a buffer is replaced (batched plans keep pointers)
+    // buffers replaced by larger ones: a graph the caller captured earlier may
+    // still name them, so they are freed only by hodlr_destroy
+    std::vector<void*> retired;
 };
 
 struct hodlr_op_s {
@@ -287,6 +290,7 @@ struct hodlr_op_s {
     double* d_tscale = nullptr;
     std::mutex ws_mu;
     std::map<void*, Workspace> ws;             // per stream
+    std::mutex aug_mu;                         // builds of d_aug
 
     // per-phase timing (hodlr_profile)
     std::vector<hipEvent_t> prof_ev;           // 2 * kPhases per record
@@ -350,6 +354,7 @@ void free_device(hodlr_op_s* op) {
         dev_free(kv.second.W);
         dev_free(kv.second.Tw);
         dev_free(kv.second.sync);
+        for (void* p : kv.second.retired) dev_free(p);
     }
     op->ws.clear();
 }
@@ -813,7 +818,8 @@ hodlr_status hodlr_create(hodlr_op* out, int64_t n, int32_t depth, const int64_t
 }
 
 hodlr_status hodlr_assign_precision(hodlr_op op, double eps, const int32_t* allowed,
-                                    int32_t n_allowed, const double* norms2, uint32_t flags) {
+                                    int32_t n_allowed, const double* xi_in, const double* norms2,
+                                    uint32_t flags) {
     if (!op) return fail(HODLR_E_ARG, "op is NULL");
     if (!(eps > 0.0 && eps < 1.0)) return fail(HODLR_E_ARG, "eps must lie in (0, 1)");
     if (n_allowed < 0 || (n_allowed > 0 && !allowed)) return fail(HODLR_E_ARG, "allowed set");
@@ -822,6 +828,10 @@ hodlr_status hodlr_assign_precision(hodlr_op op, double eps, const int32_t* allo
     if ((flags & HODLR_ACC_FP32) && (flags & HODLR_ACC_FP64))
         return fail(HODLR_E_ARG, "HODLR_ACC_FP32 and HODLR_ACC_FP64 both set");
     const int depth = op->depth;
+    if (xi_in)
+        for (int k = 0; k < depth; ++k)
+            if (!(xi_in[k] >= 0.0) || std::isinf(xi_in[k]))
+                return fail(HODLR_E_ARG, "xi[%d] is negative, infinite or NaN", k);
     // nrmAll, ||H_b||_F^2 and their per-level maxima
     double all = 0.0;
     std::vector<double> lvl(depth, 0.0), bn2(op->nb, 0.0);
@@ -834,7 +844,7 @@ hodlr_status hodlr_assign_precision(hodlr_op op, double eps, const int32_t* allo
             lvl[op->blocks[b].level - 1] = std::max(lvl[op->blocks[b].level - 1], v);
         }
         if (!(all >= 0.0)) return fail(HODLR_E_ARG, "norms2[0] is negative or NaN");
-    } else {
+    } else if (!xi_in || (flags & HODLR_PER_BLOCK)) {
         // ||U V^T||_F^2 = sum((U^T U) .* (V^T V)); ||H~||_F^2 adds the leaves
         std::vector<double> nb2(op->nb, 0.0);
         parallel_for(op->nb, [&](int64_t b) {
@@ -861,21 +871,21 @@ hodlr_status hodlr_assign_precision(hodlr_op op, double eps, const int32_t* allo
     // candidates: fp64 (the working precision) and the allowed set
     std::vector<int> cand = {F64};
     for (int i = 0; i < n_allowed; ++i) cand.push_back(allowed[i]);
-    // the rule for squared norm v at level k: (xi, u', format or -1)
-    auto choose = [&](double v, int k, double* x_out, double* u_out) {
-        const double x = all > 0.0 ? std::sqrt(v / all) : 0.0;
+    // the rule for xi at level k: (u', format or -1)
+    auto choose = [&](double x, int k, double* u_out) {
         const double u1 = (x == 0.0) ? INFINITY : eps / (std::sqrt(std::ldexp(1.0, k)) * x);
         int best = -1;
         for (int f : cand)
             if (unit_roundoff(f) <= u1 && (best < 0 || unit_roundoff(f) > unit_roundoff(best))) best = f;
-        *x_out = x;
         *u_out = u1;
         return best;
     };
+    auto xi_of = [&](double v) { return all > 0.0 ? std::sqrt(v / all) : 0.0; };
     std::vector<int32_t> fmt(depth), bad(depth);
     std::vector<double> xi(depth), up(depth);
     for (int k = 1; k <= depth; ++k) {
-        const int best = choose(lvl[k - 1], k, &xi[k - 1], &up[k - 1]);
+        xi[k - 1] = xi_in ? xi_in[k - 1] : xi_of(lvl[k - 1]);
+        const int best = choose(xi[k - 1], k, &up[k - 1]);
         fmt[k - 1] = best < 0 ? F64 : best;
         bad[k - 1] = best < 0 ? 1 : 0;
     }
@@ -883,8 +893,8 @@ hodlr_status hodlr_assign_precision(hodlr_op op, double eps, const int32_t* allo
     if (flags & HODLR_PER_BLOCK) {
         bfmt.assign(op->nb, F64);
         for (int b = 0; b < op->nb; ++b) {
-            double x, u1;
-            const int best = choose(bn2[b], op->blocks[b].level, &x, &u1);
+            double u1;
+            const int best = choose(xi_of(bn2[b]), op->blocks[b].level, &u1);
             bfmt[b] = best < 0 ? F64 : best;
         }
     }
@@ -994,6 +1004,26 @@ hodlr_status hodlr_get_block(hodlr_op op, int32_t block, hodlr_block_info* info)
     return ok();
 }
 
+hodlr_status hodlr_query(hodlr_op op, hodlr_query_info* q, int64_t* leaf_bounds, int32_t* ranks) {
+    if (!op || !q) return fail(HODLR_E_ARG, "NULL argument");
+    std::memset(q, 0, sizeof(*q));
+    hodlr_status r = hodlr_get_info(op, &q->info);
+    if (r != HODLR_OK) return r;
+    for (int k = 0; k < op->depth; ++k) {
+        q->level_dtype[k] = op->level_fmt[k];
+        q->insufficient[k] = op->insufficient[k];
+        q->xi[k] = op->xi[k];
+        q->u_prime[k] = op->uprime[k];
+    }
+    q->per_block = op->block_fmt.empty() ? 0 : 1;
+    if (leaf_bounds) {
+        const int64_t* lb = op->bounds.data() + ((int64_t(1) << op->depth) - 1) + op->depth;
+        std::memcpy(leaf_bounds, lb, sizeof(int64_t) * size_t(op->nleaves + 1));
+    }
+    if (ranks) std::memcpy(ranks, op->rank.data(), sizeof(int32_t) * size_t(op->nb));
+    return ok();
+}
+
 hodlr_status hodlr_export_block(hodlr_op op, int32_t block, void* u_codes, int8_t* u_exp,
                                 void* v_codes, int8_t* v_exp, int32_t from_device) {
     if (!op) return fail(HODLR_E_ARG, "op is NULL");
@@ -1055,9 +1085,26 @@ namespace {
 // every leaf entry and every generator stored in a format wider than
 // fp16's range (fp64, fp32, bf16) must be finite in fp16 (E_RANGE
 // otherwise); the narrow stored formats are column-scaled into range.
+//
+// Built once per assignment under the handle's aug_mu: the first caller
+// enqueues the build on its stream and waits for it before marking the
+// operand ready, so a product on any other stream that finds it ready
+// reads a finished operand.  The build allocates, so it cannot happen
+// while `stream` is being captured (E_STATE: run one product outside the
+// capture first).
 hodlr_status ensure_aug(hodlr_op_s* op, int32_t w, const KParams& kp, void* stream) {
     const int slot = w == HODLR_BF16 ? 0 : 1;
+    std::lock_guard<std::mutex> lk(op->aug_mu);
     if (op->d_aug[slot] && op->aug_gen[slot] == op->gen) return HODLR_OK;
+    {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        hipError_t e = hipStreamIsCapturing(static_cast<hipStream_t>(stream), &cap);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+        if (cap != hipStreamCaptureStatusNone)
+            return fail(HODLR_E_STATE, "the %s operand of this assignment is built on the first %s product, "
+                        "which cannot run under stream capture; run one product outside the capture first",
+                        w == HODLR_BF16 ? "bf16" : "fp16", w == HODLR_BF16 ? "bf16" : "fp16");
+    }
     if (w == HODLR_FP16) {
         std::atomic<int> bad{-1};
         parallel_for(op->nleaves, [&](int64_t i) {
@@ -1091,27 +1138,69 @@ hodlr_status ensure_aug(hodlr_op_s* op, int32_t w, const KParams& kp, void* stre
     k2.aug = op->d_aug[slot];
     const int he = launch_build_aug(k2, slot, stream);
     if (he != 0) return fail(HODLR_E_DEVICE, "augmented operand: %s", hipGetErrorString(hipError_t(he)));
+    const hipError_t se = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (se != hipSuccess) return hip_fail(se, "building the augmented operand");
     op->aug_gen[slot] = op->gen;
     return HODLR_OK;
+}
+
+// Bytes of each workspace buffer one product needs.
+struct WsNeeds {
+    int64_t partial, T, xpad, W, Tw, sync;
+};
+
+WsNeeds workspace_needs(const hodlr_op_s* op, int nrhs, int xy_bytes) {
+    WsNeeds n{};
+    // padded X: when some leaf is padded, and for the matrix-core path (nrhs >= kWideMin),
+    // which reads X with 16-byte vector loads and copies it when it is not aligned
+    // (the low working precision path, 2-byte X, always runs on the matrix cores)
+    const bool lowp = xy_bytes == 2;
+    n.partial = std::max<int64_t>(1, op->total_item_rank * nrhs) * 8;
+    n.T = std::max<int64_t>(1, op->total_rank * nrhs) * 8;
+    n.xpad = (op->padded || nrhs >= kWideMin || lowp) ? op->npad * nrhs * xy_bytes : 0;
+    n.W = (nrhs < kWideMin && !lowp) ? op->npad * nrhs * 8 : 0;
+    n.Tw = lowp ? std::max<int64_t>(1, op->total_rank32 * nrhs) * 2 : 0;
+    n.sync = sync_words(op->nb) * int64_t(sizeof(int32_t));
+    return n;
+}
+
+// The operator's part of the launch parameters (everything but the workspace).
+void fill_kparams(const hodlr_op_s* op, KParams* kp) {
+    kp->fac = op->d_fac;
+    kp->leafd = op->d_leaf;
+    kp->blocks = op->d_blocks;
+    kp->leaves = op->d_leaves;
+    kp->citems = op->d_citems;
+    kp->etiles = op->d_etiles;
+    kp->tscale = op->d_tscale;
+    kp->npad = op->npad;
+    kp->max_leaf = op->max_leaf;
+    kp->max_rank_path = op->max_rank_path;
+    kp->max_tstage = op->max_tstage;
+    kp->max_kp = op->max_kp;
+    kp->max_block_rank = op->max_block_rank;
+    kp->max_items_rank = op->max_items_rank;
+    kp->depth = op->depth;
+    kp->nblocks = op->nb;
+    kp->nleaves = op->nleaves;
+    kp->ncitems = int32_t(op->citems.size());
+    kp->netiles = int32_t(op->etiles.size());
+    kp->padded = op->padded ? 1 : 0;
 }
 
 hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, int xy_bytes, KParams* kp,
                                uint64_t* ws_gen = nullptr) {
     std::lock_guard<std::mutex> lk(op->ws_mu);
     Workspace& w = op->ws[stream];
-    const int64_t need_p = std::max<int64_t>(1, op->total_item_rank * nrhs);
-    const int64_t need_t = std::max<int64_t>(1, op->total_rank * nrhs);
-    // padded X: when some leaf is padded, and for the matrix-core path (nrhs >= kWideMin),
-    // which reads X with 16-byte vector loads and copies it when it is not aligned
-    // (the low working precision path, 2-byte X, always runs on the matrix cores)
-    const bool lowp = xy_bytes == 2;
-    const int64_t need_x = (op->padded || nrhs >= kWideMin || lowp) ? op->npad * nrhs * xy_bytes : 0;
+    const WsNeeds need = workspace_needs(op, nrhs, xy_bytes);
     auto grow = [&](void** ptr, int64_t* cap, int64_t bytes, const char* what) -> hodlr_status {
         if (bytes <= *cap) return HODLR_OK;
         if (*ptr) {
-            hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
-            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-            dev_free(*ptr);
+            // the old buffer stays allocated (retired): work already enqueued, and any graph
+            // captured with it, keep reading valid memory; grow at least twofold so the
+            // retired buffers never hold more than the current one
+            w.retired.push_back(*ptr);
+            bytes = std::max(bytes, 2 * *cap);
             *ptr = nullptr;
             *cap = 0;
         }
@@ -1126,48 +1215,26 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, int xy_by
         return HODLR_OK;
     };
     hodlr_status r;
-    if ((r = grow(reinterpret_cast<void**>(&w.partial), &w.cap_partial, need_p * 8, "partials")) != HODLR_OK)
+    if ((r = grow(reinterpret_cast<void**>(&w.partial), &w.cap_partial, need.partial, "partials")) != HODLR_OK)
         return r;
-    if ((r = grow(reinterpret_cast<void**>(&w.T), &w.cap_T, need_t * 8, "T")) != HODLR_OK) return r;
-    if (need_x && (r = grow(&w.xpad, &w.cap_xpad, need_x, "padded X")) != HODLR_OK) return r;
-    const int64_t need_w = (nrhs < kWideMin && !lowp) ? op->npad * nrhs * 8 : 0;
-    if (need_w && (r = grow(reinterpret_cast<void**>(&w.W), &w.cap_W, need_w, "leaf products")) != HODLR_OK)
+    if ((r = grow(reinterpret_cast<void**>(&w.T), &w.cap_T, need.T, "T")) != HODLR_OK) return r;
+    if (need.xpad && (r = grow(&w.xpad, &w.cap_xpad, need.xpad, "padded X")) != HODLR_OK) return r;
+    if (need.W && (r = grow(reinterpret_cast<void**>(&w.W), &w.cap_W, need.W, "leaf products")) != HODLR_OK)
         return r;
-    const int64_t need_tw = lowp ? std::max<int64_t>(1, op->total_rank32 * nrhs) * 2 : 0;
-    if (need_tw && (r = grow(&w.Tw, &w.cap_Tw, need_tw, "T in the working precision")) != HODLR_OK) return r;
-    const int64_t need_s = sync_words(op->nb) * int64_t(sizeof(int32_t));
-    if (need_s > w.cap_sync) {
-        if ((r = grow(reinterpret_cast<void**>(&w.sync), &w.cap_sync, need_s, "counters")) != HODLR_OK) return r;
-        hipError_t e = hipMemset(w.sync, 0, size_t(need_s));
+    if (need.Tw && (r = grow(&w.Tw, &w.cap_Tw, need.Tw, "T in the working precision")) != HODLR_OK) return r;
+    if (need.sync > w.cap_sync) {
+        if ((r = grow(reinterpret_cast<void**>(&w.sync), &w.cap_sync, need.sync, "counters")) != HODLR_OK) return r;
+        hipError_t e = hipMemset(w.sync, 0, size_t(w.cap_sync));
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "clearing counters");
     }
-    kp->fac = op->d_fac;
-    kp->leafd = op->d_leaf;
-    kp->blocks = op->d_blocks;
-    kp->leaves = op->d_leaves;
-    kp->citems = op->d_citems;
-    kp->etiles = op->d_etiles;
-    kp->tscale = op->d_tscale;
+    fill_kparams(op, kp);
     kp->partial = w.partial;
     kp->T = w.T;
     kp->xpad = w.xpad;
     kp->W = w.W;
     kp->Tw = w.Tw;
     kp->sync = w.sync;
-    kp->npad = op->npad;
-    kp->max_leaf = op->max_leaf;
-    kp->max_rank_path = op->max_rank_path;
-    kp->max_tstage = op->max_tstage;
-    kp->max_kp = op->max_kp;
-    kp->max_block_rank = op->max_block_rank;
-    kp->max_items_rank = op->max_items_rank;
-    kp->depth = op->depth;
-    kp->nblocks = op->nb;
-    kp->nleaves = op->nleaves;
-    kp->ncitems = int32_t(op->citems.size());
-    kp->netiles = int32_t(op->etiles.size());
-    kp->padded = op->padded ? 1 : 0;
     if (ws_gen) *ws_gen = w.gen;
     return HODLR_OK;
 }
@@ -1192,6 +1259,7 @@ struct BatchPlan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t last_use = 0;
+    bool captured = false;   // recorded into a caller's graph: kept until an operator of it is destroyed
     ~BatchPlan() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1200,7 +1268,11 @@ struct BatchPlan {
 };
 
 std::mutex g_batch_mu;
-std::map<std::vector<uint64_t>, std::unique_ptr<BatchPlan>> g_plans;
+// Deliberately never destroyed: a static map would free its plans' graphs
+// and device buffers from the library's static destructor, after the HIP
+// runtime may already have shut down at process exit.  Plans of destroyed
+// operators are freed by hodlr_destroy (batch_forget).
+auto& g_plans = *new std::map<std::vector<uint64_t>, std::unique_ptr<BatchPlan>>();
 uint64_t g_batch_clock = 0;
 constexpr size_t kMaxPlans = 32;
 
@@ -1482,12 +1554,15 @@ hodlr_status batch_run(const hodlr_op* ops, int count, const void* const* X, con
         if (capturing)
             return fail(HODLR_E_STATE, "batch not seen before on this stream with these arguments; run it "
                                        "once outside capture first");
-        if (g_plans.size() >= kMaxPlans) {            // drop the least recently used plan
-            auto lru = g_plans.begin();
+        if (g_plans.size() >= kMaxPlans) {            // drop the least recently used plan no graph of the
+            auto lru = g_plans.end();                   // caller's holds (those stay until an operator goes)
             for (auto q = g_plans.begin(); q != g_plans.end(); ++q)
-                if (q->second->last_use < lru->second->last_use) lru = q;
-            (void)hipDeviceSynchronize();
-            g_plans.erase(lru);
+                if (!q->second->captured && (lru == g_plans.end() || q->second->last_use < lru->second->last_use))
+                    lru = q;
+            if (lru != g_plans.end()) {
+                (void)hipDeviceSynchronize();
+                g_plans.erase(lru);
+            }
         }
         std::unique_ptr<BatchPlan> plan(new (std::nothrow) BatchPlan);
         if (!plan) return fail(HODLR_E_NOMEM, "batch plan");
@@ -1500,6 +1575,7 @@ hodlr_status batch_run(const hodlr_op* ops, int count, const void* const* X, con
     }
     BatchPlan* plan = it->second.get();
     plan->last_use = ++g_batch_clock;
+    if (capturing) plan->captured = true;
     if (capturing || !plan->exec)
         e = launch_groups(plan->groups[plan->order], s);     // the caller's capture records the launches
     else
@@ -1513,7 +1589,8 @@ hodlr_status batch_run(const hodlr_op* ops, int count, const void* const* X, con
 extern "C" {
 
 hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int64_t ldy,
-                          int32_t nrhs, int32_t xy_dtype, void* stream) {
+                          int32_t nrhs, int32_t xy_dtype, hipStream_t hstream) {
+    void* stream = static_cast<void*>(hstream);
     if (!op) return fail(HODLR_E_ARG, "op is NULL");
     if (op->device < 0) return fail(HODLR_E_STATE, "host-only handle: no product");
     if (nrhs < 1) return fail(HODLR_E_ARG, "nrhs must be >= 1");
@@ -1553,7 +1630,8 @@ hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int6
 
 hodlr_status hodlr_matvec_batched(const hodlr_op* ops, int32_t count, const void* const* X,
                                   const int64_t* ldx, void* const* Y, const int64_t* ldy,
-                                  const int32_t* nrhs, const int32_t* xy_dtype, void* stream) {
+                                  const int32_t* nrhs, const int32_t* xy_dtype, hipStream_t hstream) {
+    void* stream = static_cast<void*>(hstream);
     if (count < 0) return fail(HODLR_E_ARG, "count < 0");
     if (count == 0) return ok();
     if (!ops || !X || !ldx || !Y || !ldy || !nrhs || !xy_dtype) return fail(HODLR_E_ARG, "NULL array");
@@ -1651,5 +1729,7 @@ const char* hodlr_status_string(hodlr_status s) {
 }
 
 const char* hodlr_last_error(void) { return g_last_error.c_str(); }
+
+const char* hodlr_last_error_message(void) { return g_last_error.c_str(); }
 
 }  // extern "C"

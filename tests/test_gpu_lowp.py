@@ -187,3 +187,30 @@ def test_fp16_range_is_checked():
     y = h.matvec(Xb)
     torch.cuda.synchronize()
     assert torch.isfinite(y.float()).all()
+
+
+def test_first_call_on_two_streams_at_once():
+    """The first bf16 product after an assignment builds the bf16 operand;
+    a product enqueued at the same time on a second stream must not read it
+    before the build has finished."""
+    case = Case("c2_s", n=2048, depth=3, eps=1e-5)
+    ref = case.library_op()
+    ref.assign_precision(case.eps, case.cfg.allowed, case.norms2)
+    X = case.cfg.X(2)[:2048]
+    Xd = H.colmajor_empty(2048, 2, torch.bfloat16, DEV)
+    Xd.copy_(torch.from_numpy(np.asfortranarray(X)).to(torch.bfloat16))
+    want = ref.matvec(Xd).clone()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        h = case.library_op()
+        h.assign_precision(case.eps, case.cfg.allowed, case.norms2)
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        Y1 = H.colmajor_empty(2048, 2, torch.bfloat16, DEV)
+        Y2 = H.colmajor_empty(2048, 2, torch.bfloat16, DEV)
+        with torch.cuda.stream(s1):
+            h.matvec(Xd, Y1, stream=s1)
+        with torch.cuda.stream(s2):
+            h.matvec(Xd, Y2, stream=s2)
+        torch.cuda.synchronize()
+        assert torch.equal(Y1, want) and torch.equal(Y2, want), rep
+        h.close()

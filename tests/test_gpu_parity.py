@@ -296,3 +296,41 @@ def test_c2_full_size_bench_workload():
     assert [lv[0] for lv in h.levels()] == a.fmt
     for nrhs in (1, 32):
         _run(case, h, a.fmt, nrhs, "fp32", "fp32", "c2-full")
+
+
+def test_captured_product_survives_workspace_growth():
+    """A product captured into a graph keeps its workspace: a later call on
+    the same stream with more right-hand sides replaces the stream's
+    workspace, and the graph must still replay correctly."""
+    case = Case("c2_s", n=4096, depth=4, eps=1e-5)
+    h = case.library_op()
+    h.assign_precision(case.eps, case.cfg.allowed, case.norms2)
+    X = case.cfg.X(32)[:4096]
+    X1 = H.colmajor_empty(4096, 1, torch.float32, DEV)
+    X1.copy_(torch.from_numpy(np.asfortranarray(X[:, :1])).float())
+    Xw = H.colmajor_empty(4096, 32, torch.float32, DEV)
+    Xw.copy_(torch.from_numpy(np.asfortranarray(X)).float())
+    Y1 = H.colmajor_empty(4096, 1, torch.float32, DEV)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        h.matvec(X1, Y1, stream=s)                # sizes this stream's workspace, outside capture
+    s.synchronize()
+    ref = Y1.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        h.matvec(X1, Y1, stream=s)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        Yw = h.matvec(Xw, stream=s)               # grows the workspace of stream s
+    s.synchronize()
+    for rep in range(3):
+        Y1.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Y1, ref), rep
+        with torch.cuda.stream(s):
+            h.matvec(Xw, Yw, stream=s)
+        s.synchronize()
+    del g

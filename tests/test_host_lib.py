@@ -248,3 +248,90 @@ def test_depth_zero_and_rank_zero_operators():
     h2 = H.Operator(n, depth, lv, U, V, device=-1)
     h2.assign_precision(1e-3, ["fp16"], None)
     assert [lvl[0] for lvl in h2.levels()] == ["fp16", "fp16"]     # xi = 0 -> coarsest
+
+
+def test_assign_with_given_xi_matches_oracle():
+    """xi passed in: the library applies the rule to exactly those values
+    (bit-identical u', formats and marks to the oracle's rule from xi),
+    including values placed on a format's threshold (a tie selects it)."""
+    c, depth, op, h = _host_op("c2_s")
+    levels = [b.level for b in T.blocks(c.n, depth)]
+    a0 = AS.assign(op.norm2_all, AS.level_max_norm2(op.norm2_blocks, levels), 1e-6, c.allowed)
+    rng = np.random.default_rng(7)
+    eps = 1e-4
+    tie = [eps / (np.sqrt(float(2 ** k)) * F.fmt("fp16").u) for k in range(1, depth + 1)]
+    for xi in (a0.xi, list(rng.uniform(1e-4, 0.5, depth)), tie, [0.0] * depth,
+               [1e9] + [0.1] * (depth - 1)):
+        for allowed in (c.allowed, ("e4m3", "e5m2", "fp16", "bf16", "fp32"), ()):
+            h.assign_precision(eps, allowed, None, xi=xi)
+            ref = AS.assign_from_xi(xi, eps, allowed)
+            got = h.levels()
+            assert [g[0] for g in got] == ref.fmt
+            assert [g[1] for g in got] == [float(x) for x in xi]
+            assert [g[2] for g in got] == ref.u_prime
+            assert [g[3] for g in got] == ref.insufficient
+    # the oracle's own xi gives the oracle's own decisions
+    h.assign_precision(1e-6, c.allowed, None, xi=a0.xi)
+    assert [g[0] for g in h.levels()] == a0.fmt
+    with pytest.raises(H.HodlrError) as e:
+        h.assign_precision(1e-6, c.allowed, None, xi=[-1.0] + [0.1] * (depth - 1))
+    assert e.value.status == 1
+    with pytest.raises(H.HodlrError):
+        h.assign_precision(1e-6, c.allowed, None, xi=[float("nan")] * depth)
+
+
+def test_query_matches_the_individual_queries():
+    c, depth, op, h = _host_op("c2_s", depth=4)
+    norms = np.concatenate([[op.norm2_all], op.norm2_blocks])
+    h.assign_precision(1e-4, ("e4m3", "fp16", "bf16", "fp32"), norms)
+    q = h.query()
+    info = h.info()
+    for k in info:
+        assert q[k] == info[k], k
+    assert q["levels"] == h.levels()
+    assert list(q["leaf_bounds"]) == T.node_bounds(c.n, depth)[depth]
+    assert list(q["ranks"]) == [u.shape[1] for u in op.U]
+    assert q["per_block"] is False
+    h.assign_precision(1e-4, ("e4m3", "fp16", "bf16", "fp32"), norms, H.PER_BLOCK)
+    assert h.query()["per_block"] is True
+
+
+def test_last_error_message_names_the_failure():
+    L = H.lib()
+    with pytest.raises(H.HodlrError):
+        H.tree_bounds(5, 2, [0, 3, 2, 4, 5])
+    msg = L.hodlr_last_error_message().decode()
+    assert msg and msg == L.hodlr_last_error().decode()
+    assert "leaf_bounds" in msg or "non-decreasing" in msg or msg
+
+
+def test_binding_refuses_mismatched_tensors():
+    """X / Y dtype, shape and device are checked before the C ABI is called
+    (a host-only handle: every tensor here is on the CPU)."""
+    torch = pytest.importorskip("torch")
+    c, depth, op, h = _host_op("c2_s", depth=3)
+    n = c.n
+
+    def cm(k, dt):                                      # n x k column-major, on the CPU
+        return torch.zeros((k, n), dtype=dt).t()
+
+    X = cm(2, torch.float32)
+    with pytest.raises(TypeError):
+        h.matvec(X, cm(2, torch.float64))
+    with pytest.raises(ValueError, match="nrhs"):
+        h.matvec(X, cm(3, torch.float32))
+    with pytest.raises(TypeError):
+        h.matvec(cm(2, torch.int32))
+    with pytest.raises(ValueError, match="GPU"):
+        h.matvec(X, cm(2, torch.float32))
+    with pytest.raises(ValueError, match="GPU"):
+        H.matvec_batched([h], [X], [cm(2, torch.float32)])
+    with pytest.raises(TypeError):
+        H.matvec_batched([h], [X], [cm(2, torch.float64)])
+    with pytest.raises(ValueError, match="nrhs"):
+        H.matvec_batched([h], [X], [cm(1, torch.float32)])
+    with pytest.raises(ValueError):
+        H.matvec_batched([h, h], [X], [X])
+    from paper_2407_21637_amd._lib import _xy_code
+    assert [_xy_code(torch.zeros(1, dtype=d)) for d in
+            (torch.float64, torch.float32, torch.bfloat16, torch.float16)] == [0, 1, 2, 3]
