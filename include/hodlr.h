@@ -245,6 +245,24 @@ hodlr_status hodlr_export_block(hodlr_op op, int32_t block, void* u_codes, int8_
 hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int64_t ldy,
                           int32_t nrhs, int32_t xy_dtype, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * product of hodlr_matvec with HODLR_FP64 or HODLR_FP32 X and Y, the same
+ * kernels and the same result bit for bit, with every workspace buffer
+ * taken from one library-owned static device array of 64 MiB per GPU
+ * (held from the first such call on a device until the process ends)
+ * instead of a per-stream workspace.  Nothing is allocated: not by the
+ * library, not by the runtime on its behalf.  A product whose workspace
+ * exceeds 64 MiB gets E_ARG (the message gives the bytes needed); bf16 /
+ * fp16 X gets E_UNSUPPORTED (that path needs a per-assignment operand).
+ * All such calls on one GPU share the array: calls that can overlap in
+ * time (different streams, other threads, other handles) race and give
+ * wrong results; serialise them, e.g. on one stream.  The arrival
+ * counters in the array are cleared by a fill kernel at the start of each
+ * call, so a captured call replays correctly. */
+hodlr_status hodlr_matvec_noalloc(hodlr_op op, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                                  int32_t nrhs, int32_t xy_dtype, hipStream_t stream);
+
 /* count independent products Y_i = A_i X_i (each as hodlr_matvec defines
  * it; the paper treats one operator at a time, this is the batch of many).
  * Operators may differ in size, depth, ranks, formats, nrhs and dtype but

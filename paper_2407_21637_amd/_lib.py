@@ -32,7 +32,7 @@ STATUS = {0: "HODLR_OK", 1: "HODLR_E_ARG", 2: "HODLR_E_STATE", 3: "HODLR_E_NOMEM
 EXPORTS = ("hodlr_depth_for_leaf", "hodlr_tree_bounds", "hodlr_tree_blocks", "hodlr_create",
            "hodlr_assign_precision", "hodlr_set_level_precisions", "hodlr_get_level",
            "hodlr_get_info", "hodlr_get_block", "hodlr_query", "hodlr_export_block", "hodlr_matvec",
-           "hodlr_matvec_batched", "hodlr_profile", "hodlr_profile_read",
+           "hodlr_matvec_noalloc", "hodlr_matvec_batched", "hodlr_profile", "hodlr_profile_read",
            "hodlr_destroy", "hodlr_status_string", "hodlr_last_error_message", "hodlr_last_error")
 # entry points that return something other than hodlr_status
 _NON_STATUS = ("hodlr_depth_for_leaf", "hodlr_status_string", "hodlr_last_error_message", "hodlr_last_error")
@@ -96,6 +96,7 @@ def lib():
         L.hodlr_query.argtypes = [vp, vp, vp, vp]
         L.hodlr_export_block.argtypes = [vp, i32, vp, vp, vp, vp, i32]
         L.hodlr_matvec.argtypes = [vp, vp, i64, vp, i64, i32, i32, vp]
+        L.hodlr_matvec_noalloc.argtypes = [vp, vp, i64, vp, i64, i32, i32, vp]
         L.hodlr_matvec_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.hodlr_profile.argtypes = [vp, i32]
         L.hodlr_profile_read.argtypes = [vp, vp, vp]
@@ -304,6 +305,14 @@ class Operator:
         xp, ldx, Y, yp, ldy, nrhs, code = self._xy(X, Y)
         _check(lib().hodlr_matvec(self._h, C.c_void_p(xp), ldx, C.c_void_p(yp), ldy, nrhs, code,
                                   _stream_ptr(stream)))
+        return Y
+
+    def matvec_noalloc(self, X, Y, stream=None):
+        """``hodlr_matvec_noalloc``: the fp64 / fp32 product with the workspace
+        in the library's static scratch array (Y must be given)."""
+        xp, ldx, Y, yp, ldy, nrhs, code = self._xy(X, Y)
+        _check(lib().hodlr_matvec_noalloc(self._h, C.c_void_p(xp), ldx, C.c_void_p(yp), ldy, nrhs, code,
+                                          _stream_ptr(stream)))
         return Y
 
     def profile(self, capacity):

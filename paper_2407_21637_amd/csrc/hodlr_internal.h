@@ -163,6 +163,22 @@ int launch_matvec_lp(const KParams& kp, const void* X, int64_t ldx, void* Y, int
                      void* stream, void* const* events, bool* ran);
 
 // ---------------------------------------------------------------------------
+// allocation-free products (hodlr_matvec_noalloc)
+// ---------------------------------------------------------------------------
+// Every workspace buffer of such a product is carved from one file-scope
+// device array (`scratch`, kernels.hip) of kScratchBytes on each GPU.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+
+// Device address of the scratch array on `device`, which must be the
+// current device.  Looked up once per device (hipGetSymbolAddress) and
+// kept; returns a hipError_t as int.
+int scratch_address(int device, void** ptr);
+
+// Zero n int32 words at p on `stream` with a fill kernel (no memset node,
+// so the call may be captured into a graph).  Returns a hipError_t as int.
+int launch_zero_words(int32_t* p, int64_t n, void* stream);
+
+// ---------------------------------------------------------------------------
 // batched products: persistent launches over many operators
 // ---------------------------------------------------------------------------
 // How one product of one operator is launched (chosen as the

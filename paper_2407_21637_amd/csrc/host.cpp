@@ -1628,6 +1628,55 @@ hodlr_status hodlr_matvec(hodlr_op op, const void* X, int64_t ldx, void* Y, int6
     return ok();
 }
 
+hodlr_status hodlr_matvec_noalloc(hodlr_op op, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                                  int32_t nrhs, int32_t xy_dtype, hipStream_t hstream) {
+    void* stream = static_cast<void*>(hstream);
+    if (!op) return fail(HODLR_E_ARG, "op is NULL");
+    if (op->device < 0) return fail(HODLR_E_STATE, "host-only handle: no product");
+    if (nrhs < 1) return fail(HODLR_E_ARG, "nrhs must be >= 1");
+    if (xy_dtype != HODLR_FP32 && xy_dtype != HODLR_FP64)
+        return fail(HODLR_E_UNSUPPORTED, "hodlr_matvec_noalloc takes HODLR_FP64 or HODLR_FP32 X and Y");
+    if (!X || !Y) return fail(HODLR_E_ARG, "X or Y is NULL");
+    if (ldx < op->n || ldy < op->n) return fail(HODLR_E_ARG, "ldx and ldy must be >= n");
+    const int xy_bytes = xy_dtype == HODLR_FP64 ? 8 : 4;
+    // the workspace carved from the scratch array: counters first, every buffer 256-byte aligned
+    const WsNeeds need = workspace_needs(op, nrhs, xy_bytes);
+    int64_t off = 0;
+    auto carve = [&](int64_t bytes) {
+        const int64_t o = off;
+        off += align_up(std::max<int64_t>(bytes, 0), 256);
+        return o;
+    };
+    const int64_t o_sync = carve(need.sync), o_part = carve(need.partial), o_T = carve(need.T);
+    const int64_t o_x = carve(need.xpad), o_W = carve(need.W);
+    if (off > int64_t(kScratchBytes))
+        return fail(HODLR_E_ARG, "this product needs %lld bytes of workspace, more than the %lld bytes of "
+                    "hodlr_matvec_noalloc's scratch; use hodlr_matvec", (long long)off, (long long)kScratchBytes);
+    hipError_t e = hipSetDevice(op->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    void* base = nullptr;
+    const int se = scratch_address(op->device, &base);
+    if (se != 0) return fail(HODLR_E_DEVICE, "scratch address: %s", hipGetErrorString(hipError_t(se)));
+    uint8_t* b8 = static_cast<uint8_t*>(base);
+    KParams kp{};
+    fill_kparams(op, &kp);
+    kp.sync = reinterpret_cast<int32_t*>(b8 + o_sync);
+    kp.partial = reinterpret_cast<double*>(b8 + o_part);
+    kp.T = reinterpret_cast<double*>(b8 + o_T);
+    kp.xpad = need.xpad ? static_cast<void*>(b8 + o_x) : nullptr;
+    kp.W = need.W ? reinterpret_cast<double*>(b8 + o_W) : nullptr;
+    // the array keeps the last call's contents: the arrival counters must start at zero
+    int he = launch_zero_words(kp.sync, need.sync / int64_t(sizeof(int32_t)), stream);
+    if (he == 0)
+        he = launch_matvec(kp, X, ldx, Y, ldy, nrhs, xy_dtype == HODLR_FP64, op->acc_double, stream, nullptr,
+                           nullptr);
+    if (he == int(hipErrorInvalidConfiguration))
+        return fail(HODLR_E_UNSUPPORTED, "leaf size %d with path rank %d needs more than 64 KB of LDS",
+                    op->max_leaf, op->max_rank_path);
+    if (he != 0) return fail(HODLR_E_DEVICE, "kernel launch: %s", hipGetErrorString(hipError_t(he)));
+    return ok();
+}
+
 hodlr_status hodlr_matvec_batched(const hodlr_op* ops, int32_t count, const void* const* X,
                                   const int64_t* ldx, void* const* Y, const int64_t* ldy,
                                   const int32_t* nrhs, const int32_t* xy_dtype, hipStream_t hstream) {

@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "hodlr_internal.h"
 
@@ -43,6 +44,48 @@
 #include "wide_path.h"
 
 namespace hodlr {
+
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free entry point
+// ---------------------------------------------------------------------------
+// One array per GPU, alive until the process ends.  In host code its name
+// stands for a host-side shadow, not for device memory: host code uses only
+// the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+__global__ __launch_bounds__(256) void k_zero_words(int32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * int64_t(256) + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) p[i] = 0;
+}
+
+}  // namespace
+
+int scratch_address(int device, void** ptr) {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return int(hipErrorInvalidDevice);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return int(e);
+        if (!p) return int(hipErrorInvalidSymbol);
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return 0;
+}
+
+int launch_zero_words(int32_t* p, int64_t n, void* stream) {
+    if (n <= 0) return 0;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_zero_words, dim3(unsigned(blocks < 1024 ? blocks : 1024)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), p, n);
+    return int(hipGetLastError());
+}
 
 int launch_matvec(const KParams& kp, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs,
                   bool xy_double, bool acc_double, void* stream, void* const* events, bool* ran) {
