@@ -224,9 +224,6 @@ constexpr int kThreads = 64 * kWaves;
 #ifndef HODLR_LEAF_UNROLL
 #define HODLR_LEAF_UNROLL 16         // leaf columns in flight per wave
 #endif
-#ifndef HODLR_EXPAND_MINW
-#define HODLR_EXPAND_MINW 2          // k_expand: minimum resident waves per SIMD
-#endif
 #ifndef HODLR_CONTRACT_MINW
 #define HODLR_CONTRACT_MINW 2
 #endif

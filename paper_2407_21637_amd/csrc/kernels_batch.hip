@@ -52,10 +52,10 @@ __global__ __launch_bounds__(kThreads, HODLR_CONTRACT_MINW) void kb_phase1(const
 }
 
 template <typename XT, typename AT, int RG, int RPL>
-__global__ __launch_bounds__(kThreads, HODLR_EXPAND_MINW) void kb_expand(const BatchOp* __restrict__ ops,
-                                                                        const WorkItem* __restrict__ w, int nw) {
+__global__ __launch_bounds__(kExpandThreads) void kb_expand(const BatchOp* __restrict__ ops,
+                                                          const WorkItem* __restrict__ w, int nw) {
     extern __shared__ double smem_d[];
-    __shared__ int s_off[kMaxDepth + 1];
+    __shared__ int s_off[2 * (kMaxDepth + 1)];
     for (int i = blockIdx.x; i < nw; i += gridDim.x) {
         const WorkItem wi = w[i];
         const BatchOp o = ops[wi.op];                  // uniform: the step's operator
@@ -110,8 +110,8 @@ hipError_t batch_narrow(const BatchGroup& g, hipStream_t s) {
         hipLaunchKernelGGL((kb_phase1<XT, AT, RG, kRPL>), dim3(g.grid[1]), dim3(kThreads), size_t(g.lds_contract), s,
                            g.ops, g.contract, g.n_contract, g.stage_cap);
     if (g.n_expand)
-        hipLaunchKernelGGL((kb_expand<XT, AT, RG, kRPL>), dim3(g.grid[3]), dim3(kThreads), size_t(g.lds_expand), s,
-                           g.ops, g.expand, g.n_expand);
+        hipLaunchKernelGGL((kb_expand<XT, AT, RG, kRPL>), dim3(g.grid[3]), dim3(kExpandThreads), size_t(g.lds_expand),
+                           s, g.ops, g.expand, g.n_expand);
     return hipGetLastError();
 }
 

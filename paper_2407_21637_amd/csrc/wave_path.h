@@ -158,50 +158,8 @@ __device__ void run_contract(const KParams& kp, int item, const XT* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// expansion tile: Y rows of one leaf = D_i x_i + sum_k U_b T_b
+// leaf tiles and expansion tiles: Y rows of one leaf = D_i x_i + sum_k U_b T_b
 // ---------------------------------------------------------------------------
-// chunk0: node-relative padded row where the tile's chunk of the U panel
-// starts; rin: the lane's first row within the tile; ld: tile rows.
-template <int F, typename CT, typename AT, int RG, int RPL>
-__device__ void expand_level(const KParams& kp, const BlockDesc& bd, int chunk0, int rin, int ld, bool act,
-                             const double* __restrict__ ts, AT acc[RPL][RG]) {
-    constexpr int S = Codec<F>::kBytes;
-    constexpr int UN = sizeof(CT) == 8 ? kUnroll / 2 : kUnroll;   // columns in flight
-    const int p = bd.rank;
-    const uint8_t* Up = kp.fac + bd.u_off + (int64_t(chunk0) * p + rin) * S;
-    CT lacc[RPL][RG];
-#pragma unroll
-    for (int i = 0; i < RPL; ++i)
-#pragma unroll
-        for (int rg = 0; rg < RG; ++rg) lacc[i][rg] = CT(0);
-    // every column of the level, UN loads in flight (the last group guarded)
-    for (int j = 0; j < p; j += UN) {
-        CT u[UN][RPL];
-#pragma unroll
-        for (int q = 0; q < UN; ++q) {
-            if (act && j + q < p)
-                Codec<F>::template load<RPL, CT>(Up + int64_t(j + q) * ld * S, u[q]);
-            else
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) u[q][i] = CT(0);
-        }
-#pragma unroll
-        for (int q = 0; q < UN; ++q) {
-            if (j + q >= p) break;
-#pragma unroll
-            for (int rg = 0; rg < RG; ++rg) {
-                const CT tv = CT(ts[rg * p + j + q]);
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) lacc[i][rg] += u[q][i] * tv;
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < RPL; ++i)
-#pragma unroll
-        for (int rg = 0; rg < RG; ++rg) acc[i][rg] += AT(lacc[i][rg]);
-}
-
 // Leaf tile of the first launch (wave path): W rows of the tile = D_i X_i,
 // summed over the four waves in fp64 and stored once (padded row space,
 // ld npad).  Lane l owns rows RPL*l.. of the tile; wave w walks columns
@@ -284,8 +242,60 @@ __device__ void run_leaf(const KParams& kp, int tile, const XT* __restrict__ X, 
 }
 
 // Expansion tile of the second launch (wave path): Y rows of one leaf tile
-// = W + sum_k U_b T_b over the tile's depth ancestor blocks; the waves'
-// partial rows are added in LDS and Y is written once.
+// = W + sum_k U_b T_b over the tile's depth ancestor blocks.
+//
+// The tile's work is cut into units of (level k, group of kUnroll columns
+// of level k's U chunk), numbered level by level, and unit u runs on wave
+// u mod kExpandWaves: every wave streams about the same number of U
+// columns whatever the ranks of the levels, so the chain of dependent
+// loads a wave walks is about (sum of the ranks) / (kUnroll x waves) long.
+// A unit's kUnroll column loads are all issued before its FMAs.  Each wave
+// accumulates its units into per-row partials; the waves' partials are
+// added in LDS in wave order, W is added and Y is written once (the order
+// of every sum is fixed, so the result is deterministic).
+constexpr int kExpandWaves = 8;
+constexpr int kExpandThreads = 64 * kExpandWaves;
+
+// columns of one unit of a level stored in format f (fp64 levels take half)
+__device__ __forceinline__ int unit_cols(int f) { return f == F64 ? kUnroll / 2 : kUnroll; }
+
+template <int F, typename CT, typename AT, int RG, int RPL>
+__device__ __forceinline__ void expand_unit(const KParams& kp, const BlockDesc& bd, int j0, int chunk0, int rin,
+                                            int ld, bool act, const double* __restrict__ ts, AT acc[RPL][RG]) {
+    constexpr int S = Codec<F>::kBytes;
+    constexpr int UN = F == F64 ? kUnroll / 2 : kUnroll;          // columns per unit (= unit_cols(F))
+    const int p = bd.rank;
+    const uint8_t* Up = kp.fac + bd.u_off + (int64_t(chunk0) * p + rin) * S;
+    CT u[UN][RPL];
+#pragma unroll
+    for (int q = 0; q < UN; ++q) {
+        if (act && j0 + q < p)
+            Codec<F>::template load<RPL, CT>(Up + int64_t(j0 + q) * ld * S, u[q]);
+        else
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) u[q][i] = CT(0);
+    }
+    CT lacc[RPL][RG];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) lacc[i][rg] = CT(0);
+#pragma unroll
+    for (int q = 0; q < UN; ++q) {
+        if (j0 + q >= p) break;
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+            const CT tv = CT(ts[rg * p + j0 + q]);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) lacc[i][rg] += u[q][i] * tv;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) acc[i][rg] += AT(lacc[i][rg]);
+}
+
 template <typename XT, typename AT, int RG, int RPL>
 __device__ void run_expand(const KParams& kp, int tile, XT* __restrict__ Y, int64_t ldy, int nrhs,
                            unsigned char* smem, int* s_off) {
@@ -296,24 +306,32 @@ __device__ void run_expand(const KParams& kp, int tile, XT* __restrict__ Y, int6
     const int wave = threadIdx.x >> 6;
     const bool act = RPL * lane < t.nr;
     const int depth = kp.depth;
-    // LDS: T of every level [sum p][RG] | wave sums [kWaves][TR]
+    // LDS: T of every level [sum p][RG] | wave sums [kExpandWaves][TR].
+    // s_off[0..depth]: T offsets of the levels (level k at s_off[k-1]);
+    // s_off[kMaxDepth+1 ..]: first unit of each level, then the unit count.
+    int* s_u0 = s_off + kMaxDepth + 1;
     double* ts = reinterpret_cast<double*>(smem);
-    // level offsets of T in LDS: thread k-1 reads level k's rank, thread 0 adds up
     if (threadIdx.x < depth) {
         const int k = threadIdx.x + 1;
-        s_off[k] = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))].rank * RG;
+        const BlockDesc& bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
+        s_off[k] = bd.rank * RG;
+        s_u0[k] = (bd.rank + unit_cols(bd.fmt) - 1) / unit_cols(bd.fmt);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int off = 0;
+        int off = 0, u0 = 0;
         for (int k = 1; k <= depth; ++k) {
-            const int r = s_off[k];
+            const int r = s_off[k], nu = s_u0[k];
             s_off[k - 1] = off;
+            s_u0[k - 1] = u0;
             off += r;
+            u0 += nu;
         }
         s_off[depth] = off;
+        s_u0[depth] = u0;
     }
     __syncthreads();
+    const int nunits = s_u0[depth];
     AT* red = reinterpret_cast<AT*>(ts + s_off[depth]);
     for (int rb = 0; rb < nrhs; rb += RG) {
         AT acc[RPL][RG];
@@ -322,7 +340,7 @@ __device__ void run_expand(const KParams& kp, int tile, XT* __restrict__ Y, int6
 #pragma unroll
             for (int rg = 0; rg < RG; ++rg) acc[i][rg] = AT(0);
         // T of every level for right-hand sides [rb, rb+RG): one pass of loads
-        for (int idx = threadIdx.x; idx < s_off[depth]; idx += kThreads) {
+        for (int idx = threadIdx.x; idx < s_off[depth]; idx += kExpandThreads) {
             int k = 1;
             while (k < depth && s_off[k] <= idx) ++k;
             const BlockDesc& bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
@@ -332,22 +350,22 @@ __device__ void run_expand(const KParams& kp, int tile, XT* __restrict__ Y, int6
             ts[idx] = (rb + rg < nrhs) ? kp.T[bd.t_off * nrhs + int64_t(rb + rg) * p + j] : 0.0;
         }
         __syncthreads();
-        // the waves take whole levels (wave w: levels w+1, w+5, ...), so the
-        // chain of dependent loads per wave is short
-        for (int k = 1 + wave; k <= depth; k += kWaves) {
+        int k = 1;
+        for (int u = wave; u < nunits; u += kExpandWaves) {
+            while (s_u0[k] <= u) ++k;                // level of unit u (units ascend by level)
             const int b = (1 << k) - 2 + (t.leaf >> (depth - k));
             const BlockDesc bd = kp.blocks[b];
-            if (bd.rank == 0) continue;
+            const int j0 = (u - s_u0[k - 1]) * unit_cols(bd.fmt);
             const int c0 = L.prow0 - bd.urow0 + t.r0;
             const int rin = RPL * lane;
             const double* tk = ts + s_off[k - 1];
             switch (bd.fmt) {
-                case F64: expand_level<F64, double, AT, RG, RPL>(kp, bd, c0, rin, t.nr, act, tk, acc); break;
-                case F32: expand_level<F32, AT, AT, RG, RPL>(kp, bd, c0, rin, t.nr, act, tk, acc); break;
-                case BF16: expand_level<BF16, AT, AT, RG, RPL>(kp, bd, c0, rin, t.nr, act, tk, acc); break;
-                case F16: expand_level<F16, AT, AT, RG, RPL>(kp, bd, c0, rin, t.nr, act, tk, acc); break;
-                case E4M3: expand_level<E4M3, AT, AT, RG, RPL>(kp, bd, c0, rin, t.nr, act, tk, acc); break;
-                default: expand_level<E5M2, AT, AT, RG, RPL>(kp, bd, c0, rin, t.nr, act, tk, acc); break;
+                case F64: expand_unit<F64, double, AT, RG, RPL>(kp, bd, j0, c0, rin, t.nr, act, tk, acc); break;
+                case F32: expand_unit<F32, AT, AT, RG, RPL>(kp, bd, j0, c0, rin, t.nr, act, tk, acc); break;
+                case BF16: expand_unit<BF16, AT, AT, RG, RPL>(kp, bd, j0, c0, rin, t.nr, act, tk, acc); break;
+                case F16: expand_unit<F16, AT, AT, RG, RPL>(kp, bd, j0, c0, rin, t.nr, act, tk, acc); break;
+                case E4M3: expand_unit<E4M3, AT, AT, RG, RPL>(kp, bd, j0, c0, rin, t.nr, act, tk, acc); break;
+                default: expand_unit<E5M2, AT, AT, RG, RPL>(kp, bd, j0, c0, rin, t.nr, act, tk, acc); break;
             }
         }
         // sum the waves' partial rows, add the leaf product; write Y once
@@ -356,10 +374,10 @@ __device__ void run_expand(const KParams& kp, int tile, XT* __restrict__ Y, int6
 #pragma unroll
             for (int i = 0; i < RPL; ++i) red[wave * TR + RPL * lane + i] = acc[i][rg];
             __syncthreads();
-            for (int r = threadIdx.x; r < TR; r += kThreads) {
+            for (int r = threadIdx.x; r < TR; r += kExpandThreads) {
                 AT sum = red[r];
 #pragma unroll
-                for (int w = 1; w < kWaves; ++w) sum += red[w * TR + r];
+                for (int w = 1; w < kExpandWaves; ++w) sum += red[w * TR + r];
                 const int lr = t.r0 + r;
                 if (r < t.nr && lr < L.m && rb + rg < nrhs)
                     Y[L.row0 + lr + ldy * (rb + rg)] =
@@ -396,10 +414,9 @@ __global__ __launch_bounds__(kThreads, HODLR_CONTRACT_MINW) void k_phase1(KParam
 }
 
 template <typename XT, typename AT, int RG, int RPL>
-__global__ __launch_bounds__(kThreads, HODLR_EXPAND_MINW) void k_expand(KParams kp, XT* __restrict__ Y, int64_t ldy,
-                                                                       int nrhs) {
+__global__ __launch_bounds__(kExpandThreads) void k_expand(KParams kp, XT* __restrict__ Y, int64_t ldy, int nrhs) {
     extern __shared__ double smem_d[];
-    __shared__ int s_off[kMaxDepth + 1];
+    __shared__ int s_off[2 * (kMaxDepth + 1)];
     run_expand<XT, AT, RG, RPL>(kp, blockIdx.x, Y, ldy, nrhs, reinterpret_cast<unsigned char*>(smem_d), s_off);
 }
 
@@ -448,7 +465,7 @@ int stage_cap(const KParams& kp, int rg) {
 
 // expansion tile LDS (wave path): T of its levels (doubles) | wave sums
 size_t lds_expand(const KParams& kp, int rg, size_t acc_bytes) {
-    return size_t(kp.max_rank_path) * rg * 8 + size_t(kWaves) * kTileRows * acc_bytes;
+    return size_t(kp.max_rank_path) * rg * 8 + size_t(kExpandWaves) * kTileRows * acc_bytes;
 }
 
 // first launch LDS: the larger of a contraction item's staging and a leaf
@@ -480,8 +497,8 @@ hipError_t launch_typed(const KParams& kp, const void* Xv, int64_t ldx, void* Yv
                        lds_phase1(kp, RG), s, kp, Xc, ldc, X, ldx, nrhs, sc);
     tm.end(1);
     tm.begin(2);
-    hipLaunchKernelGGL((k_expand<XT, AT, RG, RPL>), dim3(kp.netiles), dim3(kThreads), lds_expand(kp, RG, sizeof(AT)),
-                       s, kp, Y, ldy, nrhs);
+    hipLaunchKernelGGL((k_expand<XT, AT, RG, RPL>), dim3(kp.netiles), dim3(kExpandThreads),
+                       lds_expand(kp, RG, sizeof(AT)), s, kp, Y, ldy, nrhs);
     tm.end(2);
     return hipGetLastError();
 }
