@@ -31,21 +31,23 @@ class QFactor:
     codes: np.ndarray     # rows x p unsigned bit patterns
     exps: np.ndarray      # p int column exponents (zeros when unscaled)
     values: np.ndarray    # rows x p fp64: decode(codes) * 2^-exps
+    scaled: bool = False  # True when the columns carry stored exponents
 
 
 def quantize(Fm: np.ndarray, fmt: str, scale_columns: bool = True) -> QFactor:
     Fm = np.asarray(Fm, dtype=np.float64)
     f = F.fmt(fmt)
     p = Fm.shape[1]
-    if scale_columns and f.name in F.SCALED and Fm.size:
+    scaled = bool(scale_columns and f.name in F.SCALED)
+    if scaled and Fm.size:
         exps = F.column_scale_exponent(f, np.abs(Fm).max(axis=0))
     else:
         exps = np.zeros(p, dtype=np.int64)
-    scaled = np.ldexp(Fm, exps[None, :]) if p else Fm
-    r = F.round_rne(f, scaled)
+    shifted = np.ldexp(Fm, exps[None, :]) if p else Fm
+    r = F.round_rne(f, shifted)
     codes = F.encode(f, r)
     values = np.ldexp(F.decode(f, codes), -exps[None, :]) if p else r
-    return QFactor(f.name, codes, exps, values)
+    return QFactor(f.name, codes, exps, values, scaled)
 
 
 @dataclass
@@ -89,11 +91,12 @@ def store_blocks(h, block_fmt, scale_columns: bool = True) -> StoredHodlr:
 
 
 def storage_bits(stored: StoredHodlr) -> int:
-    """Bits of the stored generators: codes plus 8 per scaled column."""
+    """Bits of the stored generators: codes plus one 8-bit exponent per
+    column of a factor stored with column scales."""
     bits = 0
     for q in list(stored.QU) + list(stored.QV):
         f = F.fmt(q.fmt)
         bits += q.codes.size * 8 * f.nbytes
-        if f.name in F.SCALED:
+        if q.scaled:
             bits += 8 * q.codes.shape[1]
     return bits
