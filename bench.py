@@ -700,7 +700,10 @@ def profile_run(args, torch, H, batch):
         hs, Xs, Ys = [], [], []
         for sp, c in zip(specs, cops):
             h = H.Operator(sp.n, sp.depth, c.leaves, c.U, c.V, device=0)
-            h.assign_precision(sp.eps, BT.ALLOWED, np.concatenate([[c.norm2_all], c.norm2_blocks]))
+            if args.fp64:
+                h.set_level_precisions(["fp64"] * sp.depth, H.ACC_FP64)
+            else:
+                h.assign_precision(sp.eps, BT.ALLOWED, np.concatenate([[c.norm2_all], c.norm2_blocks]))
             dt = torch.float64 if sp.x_dtype == "fp64" else torch.float32
             X = H.colmajor_empty(sp.n, sp.nrhs, dt, "cuda:0")
             X.copy_(torch.from_numpy(np.asfortranarray(sp.X())).to(dt))
@@ -713,7 +716,10 @@ def profile_run(args, torch, H, batch):
         cfg = CF.get(args.workload)
         op = build_operator(cfg, H)
         h = H.Operator(cfg.n, cfg.depth, op.leaves, op.U, op.V, device=0)
-        h.assign_precision(cfg.eps, cfg.allowed, np.concatenate([[op.norm2_all], op.norm2_blocks]))
+        if args.fp64:
+            h.set_level_precisions(["fp64"] * cfg.depth, H.ACC_FP64)
+        else:
+            h.assign_precision(cfg.eps, cfg.allowed, np.concatenate([[op.norm2_all], op.norm2_blocks]))
         nrhs = args.nrhs if args.nrhs is not None else cfg.nrhs[0]
         if args.working:
             from oracle import formats as OF
@@ -746,6 +752,8 @@ def main():
     ap.add_argument("--profile-run", action="store_true",
                     help="only the timed products of --workload (for running under rocprofv3)")
     ap.add_argument("--warm", action="store_true", help="profile runs: warm graph replays instead of cold")
+    ap.add_argument("--fp64", action="store_true",
+                    help="profile runs: every level stored in fp64 with fp64 accumulation (the uniform baseline)")
     ap.add_argument("--working", choices=["bf16", "fp16"], default=None,
                     help="profile runs: the product in this low working precision")
     ap.add_argument("--kernel-hash", action="store_true",

@@ -277,11 +277,15 @@ hodlr_status hodlr_matvec_noalloc(hodlr_op op, const void* X, int64_t ldx, void*
  * X/Y pointers, leading dimensions, nrhs, dtypes, stream) builds a plan:
  * it uploads the work lists (device memory held until a handle in it is
  * destroyed or, unless a caller's graph has recorded the plan's launches,
- * 32 newer plans evict it), times the candidate launch shapes
- * on `stream` (work order longest-first or as given; 1, 2, 4 or 8
- * workgroups per compute unit; skipped when the environment sets
- * HODLR_BATCH_TUNE=0), keeps the fastest and captures the launches into a
- * HIP graph.  Later calls with the same signature replay that graph.  On a
+ * 32 newer plans evict it), picks the shape of every launch (one
+ * variant's one phase) on `stream`: work order longest-first or as given,
+ * 1, 2, 4 or 8 workgroups per compute unit, each candidate timed alone,
+ * and captures the launches into a HIP graph.  Choices are cached by the
+ * device's architecture and the launch's shape class, in memory and in the
+ * text file HODLR_TUNE_CACHE (default $HOME/.cache/hodlr/batch_tune.txt;
+ * "off": memory only), so plans of known shapes skip the timing;
+ * HODLR_BATCH_TUNE=0 skips tuning.  Every shape gives the same result bit
+ * for bit.  Later calls with the same signature replay that graph.  On a
  * stream that is being captured the launches are recorded into the
  * caller's graph instead; that needs a plan made by an earlier call outside
  * capture (E_STATE otherwise), since nothing may be allocated during a

@@ -29,6 +29,9 @@ ARCH = os.environ.get("HODLR_OFFLOAD_ARCH", "gfx950")
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
+# compile-time tuning parameters (hodlr_internal.h, dev_common.h), e.g.
+# HODLR_BUILD_DEFINES="HODLR_ITEM_KB=128 HODLR_U_UNROLL=16"
+DEFINES = [f"-D{d}" for d in os.environ.get("HODLR_BUILD_DEFINES", "").split() if d]
 
 
 def _hipcc():
@@ -69,12 +72,12 @@ def build(verbose: bool = False) -> str:
     with tempfile.TemporaryDirectory(prefix="hodlr_build_") as tmp:
         host_o = os.path.join(tmp, "host.o")
         objs = [host_o]
-        cmds = [[hipcc, "-std=c++17", "-O2", "-fPIC", "-Wall", "-c", *inc,
+        cmds = [[hipcc, "-std=c++17", "-O2", "-fPIC", "-Wall", "-c", *DEFINES, *inc,
                  os.path.join(CSRC, "host.cpp"), "-o", host_o]]
         for tu in DEVICE_TUS:
             o = os.path.join(tmp, tu.replace(".hip", ".o"))
             objs.append(o)
-            cmds.append([hipcc, "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-c", *inc,
+            cmds.append([hipcc, "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS, *DEFINES, "-c", *inc,
                          "-x", "hip", os.path.join(CSRC, tu), "-o", o])
         # the machine-ceiling probe (a standalone program, not linked into the library)
         tmp_cal = os.path.join(tmp, "calibrate")

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cfloat>
 #include <cmath>
@@ -13,10 +14,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <new>
+#include <sys/stat.h>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1245,16 +1248,30 @@ hodlr_status prepare_workspace(hodlr_op_s* op, void* stream, int nrhs, int xy_by
 // A plan holds, for one batch signature (operators with their image and
 // workspace generations, X/Y pointers and leading dimensions, nrhs, dtypes,
 // stream), the device copies of the per-operator launch records and of the
-// work lists of every kernel-variant group, the launch shape chosen by the
-// autotuner, and a HIP graph of the launches.  The autotuner times every
-// candidate (work order: longest first or natural; persistent grid: 1, 2,
-// 4 or 8 workgroups per compute unit) on the caller's stream the first time
-// a signature is seen, unless the stream is capturing or HODLR_BATCH_TUNE=0.
+// work lists of every kernel-variant group, the launch shape the autotuner
+// chose for each launch, and a HIP graph of the launches.
+//
+// The autotuner picks, separately for every launch (one group's one
+// phase), the work order (longest item first, or as the operators were
+// given) and the persistent grid (1, 2, 4 or 8 workgroups per compute
+// unit): each candidate launch runs alone, four times, on the caller's
+// stream the first time a signature is seen (the groups run one after
+// another, so the best launch of each is the best batch).  Choices are
+// kept in a tuning cache keyed by the device's architecture and the
+// launch's shape class (variant, phase, and the number of work items and
+// their total cost rounded to powers of two), in memory and in a text
+// file (HODLR_TUNE_CACHE, default $HOME/.cache/hodlr/batch_tune.txt;
+// HODLR_TUNE_CACHE=off keeps it in memory only), so later plans of the
+// same shapes skip the timing.  HODLR_BATCH_TUNE=0 skips tuning (longest
+// first, 2 workgroups per compute unit).  Any choice gives the same
+// result bit for bit: a work item's arithmetic does not depend on which
+// workgroup runs it.
 struct BatchPlan {
     std::vector<uint64_t> uids;
     void* d_buf = nullptr;
     std::vector<BatchGroup> groups[2];   // [order]: 0 longest first, 1 natural
-    int order = 0, mult = 2;
+    std::vector<BatchGroup> tuned;       // the launches as run: per phase its order's list and grid
+    std::vector<std::array<std::string, 4>> shape;   // tuning-cache class of each group's phases
     float tuned_ms = 0.0f;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1291,13 +1308,6 @@ int compute_units(int device) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
         cus = 256;
     return cus;
-}
-
-void set_grids(std::vector<BatchGroup>& gs, int cus, int mult) {
-    for (auto& g : gs) {
-        const int32_t n[4] = {g.n_padx, g.n_contract, g.n_reduce, g.n_expand};
-        for (int ph = 0; ph < 4; ++ph) g.grid[ph] = std::max(1, std::min(n[ph], cus * mult));
-    }
 }
 
 hipError_t launch_groups(const std::vector<BatchGroup>& gs, hipStream_t s) {
@@ -1452,50 +1462,166 @@ hodlr_status build_plan(const hodlr_op* ops, int count, const void* const* X, co
         }
     }
     for (int i = 0; i < count; ++i) plan->uids.push_back(ops[i]->uid);
+    // the tuning-cache class of every launch: variant, phase, work items and cost (powers of two)
+    auto lg = [](int64_t v) { int b = 0; while ((int64_t(1) << b) < v) ++b; return b; };
+    for (auto& kv : groups) {
+        std::array<std::string, 4> cls;
+        for (int ph = 0; ph < 4; ++ph) {
+            int64_t cost = 0;
+            for (auto& w : kv.second.work[ph]) cost += w.first;
+            char buf[160];
+            std::snprintf(buf, sizeof(buf), "x%d.a%d.w%d.r%d.ph%d.n%d.c%d", kv.first[0], kv.first[1], kv.first[2],
+                          kv.first[3], ph, lg(int64_t(kv.second.work[ph].size())), lg(cost));
+            cls[ph] = buf;
+        }
+        plan->shape.push_back(cls);
+    }
     return ok();
+}
+
+// ---- tuning cache ---------------------------------------------------------
+struct TuneChoice {
+    int order, mult;
+};
+std::mutex g_tune_mu;
+// never destroyed (see g_plans); loaded from the file on first use
+auto& g_tune = *new std::map<std::string, TuneChoice>();
+bool g_tune_loaded = false;
+
+std::string tune_file() {
+    const char* env = std::getenv("HODLR_TUNE_CACHE");
+    if (env && std::strcmp(env, "off") == 0) return "";
+    if (env && env[0]) return env;
+    const char* home = std::getenv("HOME");
+    if (!home || !home[0]) return "";
+    return std::string(home) + "/.cache/hodlr/batch_tune.txt";
+}
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const std::string f = tune_file();
+    if (f.empty()) return;
+    std::ifstream in(f);
+    std::string key;
+    int o, m;
+    while (in >> key >> o >> m)
+        if ((o == 0 || o == 1) && (m == 1 || m == 2 || m == 4 || m == 8)) g_tune[key] = TuneChoice{o, m};
+}
+
+void tune_store_locked(const std::string& key, TuneChoice c) {
+    g_tune[key] = c;
+    const std::string f = tune_file();
+    if (f.empty()) return;
+    // create the file's directories (failures show up as an unwritable file, which is ignored)
+    for (size_t q = f.find('/', 1); q != std::string::npos; q = f.find('/', q + 1))
+        (void)::mkdir(f.substr(0, q).c_str(), 0755);
+    std::ofstream out(f, std::ios::app);
+    if (out) out << key << ' ' << c.order << ' ' << c.mult << '\n';
+}
+
+std::string arch_name(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        (void)hipGetLastError();
+        return "unknown";
+    }
+    std::string a = prop.gcnArchName;
+    for (char& ch : a)
+        if (ch == ' ') ch = '_';
+    char buf[32];
+    std::snprintf(buf, sizeof(buf), ".cu%d", prop.multiProcessorCount);
+    return a + buf;
+}
+
+// One group's launch of phase ph alone: the other phases' counts set to 0.
+BatchGroup phase_only(const BatchGroup& g, int ph) {
+    BatchGroup o = g;
+    if (ph != 0) o.n_padx = 0;
+    if (ph != 1) o.n_contract = 0;
+    if (ph != 2) o.n_reduce = 0;
+    if (ph != 3) o.n_expand = 0;
+    return o;
+}
+
+int phase_count(const BatchGroup& g, int ph) {
+    return ph == 0 ? g.n_padx : ph == 1 ? g.n_contract : ph == 2 ? g.n_reduce : g.n_expand;
+}
+
+// Set phase ph of `dst` to order `ord`'s work list with `mult` workgroups per CU.
+void apply_choice(BatchGroup& dst, const BatchPlan* plan, size_t gi, int ph, TuneChoice c, int cus) {
+    const BatchGroup& src = plan->groups[c.order][gi];
+    if (ph == 0) dst.padx = src.padx;
+    if (ph == 1) dst.contract = src.contract;
+    if (ph == 2) dst.reduce = src.reduce;
+    if (ph == 3) dst.expand = src.expand;
+    dst.grid[ph] = std::max(1, std::min(phase_count(src, ph), cus * c.mult));
 }
 
 hodlr_status tune_plan(BatchPlan* plan, int device, hipStream_t s) {
     const int cus = compute_units(device);
+    plan->tuned = plan->groups[0];
     const char* env = std::getenv("HODLR_BATCH_TUNE");
-    if (env && env[0] == '0') {
-        set_grids(plan->groups[plan->order], cus, plan->mult);
-        return ok();
-    }
+    const bool timing = !(env && env[0] == '0');
+    const std::string arch = arch_name(device);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (timing && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
         if (e0) (void)hipEventDestroy(e0);
         (void)hipGetLastError();
         return fail(HODLR_E_DEVICE, "events for the batch autotuner");
     }
-    float best = -1.0f;
-    const int mults[4] = {1, 2, 4, 8};
     hodlr_status st = HODLR_OK;
-    for (int ord = 0; ord < 2 && st == HODLR_OK; ++ord)
-        for (int m : mults) {
-            set_grids(plan->groups[ord], cus, m);
-            hipError_t e = launch_groups(plan->groups[ord], s);     // warm-up
-            if (e == hipSuccess) e = hipEventRecord(e0, s);
-            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = launch_groups(plan->groups[ord], s);
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) {
-                st = hip_fail(e, "batch autotuner");
-                break;
+    float total = 0.0f;
+    for (size_t gi = 0; gi < plan->tuned.size() && st == HODLR_OK; ++gi)
+        for (int ph = 0; ph < 4 && st == HODLR_OK; ++ph) {
+            if (phase_count(plan->groups[0][gi], ph) == 0) continue;
+            TuneChoice best{0, 2};
+            const std::string key = arch + "|" + plan->shape[gi][ph];
+            bool have = false;
+            {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                tune_load_locked();
+                auto it = g_tune.find(key);
+                if (it != g_tune.end()) {
+                    best = it->second;
+                    have = true;
+                }
             }
-            if (best < 0.0f || ms < best) {
-                best = ms;
-                plan->order = ord;
-                plan->mult = m;
+            if (timing && !have) {
+                float best_ms = -1.0f;
+                const int mults[4] = {1, 2, 4, 8};
+                for (int ord = 0; ord < 2 && st == HODLR_OK; ++ord)
+                    for (int m : mults) {
+                        BatchGroup cand = plan->tuned[gi];
+                        apply_choice(cand, plan, gi, ph, TuneChoice{ord, m}, cus);
+                        const std::vector<BatchGroup> one = {phase_only(cand, ph)};
+                        hipError_t e = launch_groups(one, s);                 // warm-up
+                        if (e == hipSuccess) e = hipEventRecord(e0, s);
+                        for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) e = launch_groups(one, s);
+                        if (e == hipSuccess) e = hipEventRecord(e1, s);
+                        if (e == hipSuccess) e = hipEventSynchronize(e1);
+                        float ms = 0.0f;
+                        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                        if (e != hipSuccess) {
+                            st = hip_fail(e, "batch autotuner");
+                            break;
+                        }
+                        if (best_ms < 0.0f || ms < best_ms) {
+                            best_ms = ms;
+                            best = TuneChoice{ord, m};
+                        }
+                    }
+                if (st != HODLR_OK) break;
+                total += best_ms / 4.0f;
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                tune_store_locked(key, best);
             }
+            apply_choice(plan->tuned[gi], plan, gi, ph, best, cus);
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     if (st != HODLR_OK) return st;
-    plan->tuned_ms = best / 3.0f;
-    set_grids(plan->groups[plan->order], cus, plan->mult);
+    plan->tuned_ms = total;
     return ok();
 }
 
@@ -1506,7 +1632,7 @@ hodlr_status capture_plan(BatchPlan* plan) {
     if (e != hipSuccess) return hip_fail(e, "capture stream");
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        const hipError_t le = launch_groups(plan->groups[plan->order], cs);
+        const hipError_t le = launch_groups(plan->tuned, cs);
         e = hipStreamEndCapture(cs, &plan->graph);
         if (e == hipSuccess) e = le;
     }
@@ -1577,7 +1703,7 @@ hodlr_status batch_run(const hodlr_op* ops, int count, const void* const* X, con
     plan->last_use = ++g_batch_clock;
     if (capturing) plan->captured = true;
     if (capturing || !plan->exec)
-        e = launch_groups(plan->groups[plan->order], s);     // the caller's capture records the launches
+        e = launch_groups(plan->tuned, s);                   // the caller's capture records the launches
     else
         e = hipGraphLaunch(plan->exec, s);
     if (e != hipSuccess) return hip_fail(e, "batched launch");

@@ -137,3 +137,27 @@ def test_batched_new_handle_set_and_duplicates(batch):
         single = it.h.matvec(it.Xd)
         torch.cuda.synchronize()
         assert torch.equal(single, it.Y)
+
+
+def test_tuned_and_untuned_launches_agree(batch, tmp_path, monkeypatch):
+    """Every launch shape the autotuner may choose gives the same result bit
+    for bit: the batch with tuning off (default shapes) equals the tuned
+    batch, and choices land in the tuning-cache file named by the
+    environment."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HODLR_TUNE_CACHE", str(cache))
+    items = batch[2:14]
+    hs, Xs = [it.h for it in items], [it.Xd for it in items]
+    Ya = [torch.empty_like(it.Y) for it in items]
+    H.matvec_batched(hs, Xs, Ya)                  # new signature (Y pointers): a tuned plan
+    torch.cuda.synchronize()
+    monkeypatch.setenv("HODLR_BATCH_TUNE", "0")
+    Yb = [torch.empty_like(it.Y) for it in items]
+    H.matvec_batched(hs, Xs, Yb)                  # another new signature, default shapes
+    torch.cuda.synchronize()
+    for k in range(len(items)):
+        assert torch.equal(Ya[k], Yb[k]), k
+    if cache.exists():                            # shapes new to this process were timed and stored
+        for line in cache.read_text().splitlines():
+            key, o, m = line.split()
+            assert "|x" in key and o in ("0", "1") and m in ("1", "2", "4", "8")
