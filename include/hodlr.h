@@ -127,6 +127,64 @@ hodlr_status hodlr_tree_bounds(int64_t n, int32_t depth, const int64_t* leaf_bou
 hodlr_status hodlr_tree_blocks(int64_t n, int32_t depth, const int64_t* leaf_bounds,
                                int64_t* desc_out);
 
+/* ---- construction on the GPU from a kernel matrix ---------------------- */
+
+/* Kernel matrices the library evaluates itself: A_ij = k(p_i, p_j) for
+ * points p_i of dimension `dim` (r = |p_i - p_j|), plus diag_shift on the
+ * diagonal; with diag_given the diagonal entries are diag_value (before
+ * the shift) instead of k(p_i, p_i). */
+#define HODLR_KERNEL_GAUSSIAN   0   /* exp(-r^2 / a), a > 0 */
+#define HODLR_KERNEL_INV_DIST   1   /* 1 / (r + a) */
+#define HODLR_KERNEL_LOG        2   /* log(r + a) */
+#define HODLR_KERNEL_EXP        3   /* exp(-r) */
+#define HODLR_KERNEL_SIGNED_INV 4   /* 1 / (x_i - x_j), 1D, needs diag_given */
+
+typedef struct {
+    int32_t kind;
+    int32_t dim;              /* 1 or 2 */
+    double a;
+    double diag_shift;
+    double diag_value;
+    int32_t diag_given;
+    int32_t reserved_;
+} hodlr_kernel;
+
+typedef struct {
+    double ms_norms;          /* squared norms of every block and leaf, leaves */
+    double ms_factors;        /* randomised truncated SVDs of the blocks */
+    double ms_total;          /* the whole call, the operator's upload included */
+    int32_t max_rank;
+    int32_t max_sketch;       /* widest sketch used */
+    int32_t sketch_rounds;    /* passes over a level's pending blocks (retries included) */
+    int32_t exact_residual;   /* 1: the truncation residual was computed exactly (eps < 1e-6) */
+} hodlr_build_report;
+
+/* Build the eps-HODLR operator of a kernel matrix on GPU `device`
+ * (Sect. 2-3): the tree of hodlr_tree_bounds for n and depth; leaves
+ * D_i = A(I_i, I_i); every off-diagonal block B replaced by U V^T with
+ * orthonormal U (eq. (3.1)) and the smallest rank p such that
+ * ||B - U V^T||_F <= eps ||B||_F (Def. 2.2 in the Frobenius norm, so that
+ * Lemma 2.4 holds), from a randomised truncated SVD whose residual is
+ * computed (exactly, when eps < 1e-6) rather than estimated, so the rule
+ * holds for the factors produced.  The matrix is evaluated on the fly on
+ * the device and never stored.  ||A||_F^2 and ||A_b||_F^2 of the original
+ * matrix (the nrmAll and nrm_k of Alg. "Adaptive-precision HODLR Format")
+ * are computed exactly in fp64 and kept with the operator:
+ * hodlr_assign_precision uses them when given neither xi nor norms2, and
+ * hodlr_get_norms returns them.  points: n x dim fp64 on the host, point i
+ * at points[i * dim] (deep-copied).  seed: the sketches' random numbers.
+ * The new operator is uniform fp64, as from hodlr_create.  E_UNSUPPORTED
+ * if a block needs a rank beyond the widest sketch (128 columns); report
+ * may be NULL. */
+hodlr_status hodlr_build_kernel(hodlr_op* out, int64_t n, int32_t depth, const double* points,
+                                const hodlr_kernel* kernel, double eps, uint64_t seed, int32_t device,
+                                hodlr_build_report* report);
+
+/* The squared Frobenius norms kept by hodlr_build_kernel: 1 + nblocks
+ * values, ||A||_F^2 then ||A_b||_F^2 in canonical order.  E_STATE for an
+ * operator made by hodlr_create. */
+hodlr_status hodlr_get_norms(hodlr_op op, double* norms2);
+
 /* ---- operator ------------------------------------------------------- */
 
 /* Create an operator from fp64 leaves (2^depth blocks, leaf i is m_i x m_i

@@ -6,8 +6,9 @@ The product Y = A_H X of Carson, Chen, Liu, "Mixed Precision HODLR Matrices"
 package only marshals arguments to that library; PyTorch supplies device
 memory and streams.
 """
-from ._lib import (ACC_FP32, ACC_FP64, DTYPES, EXPORTS, NO_COLUMN_SCALE, PER_BLOCK, HodlrError, Operator,
-                   colmajor_empty, depth_for_leaf, lib, matvec_batched, tree_blocks, tree_bounds)
+from ._lib import (ACC_FP32, ACC_FP64, DTYPES, EXPORTS, KERNELS, NO_COLUMN_SCALE, PER_BLOCK, HodlrError, Operator,
+                   build_kernel, colmajor_empty, depth_for_leaf, lib, matvec_batched, tree_blocks, tree_bounds)
 
-__all__ = ["ACC_FP32", "ACC_FP64", "DTYPES", "EXPORTS", "NO_COLUMN_SCALE", "PER_BLOCK", "HodlrError", "Operator",
-           "colmajor_empty", "depth_for_leaf", "lib", "matvec_batched", "tree_blocks", "tree_bounds"]
+__all__ = ["ACC_FP32", "ACC_FP64", "DTYPES", "EXPORTS", "KERNELS", "NO_COLUMN_SCALE", "PER_BLOCK", "HodlrError",
+           "Operator", "build_kernel", "colmajor_empty", "depth_for_leaf", "lib", "matvec_batched", "tree_blocks",
+           "tree_bounds"]

@@ -33,7 +33,10 @@ EXPORTS = ("hodlr_depth_for_leaf", "hodlr_tree_bounds", "hodlr_tree_blocks", "ho
            "hodlr_assign_precision", "hodlr_set_level_precisions", "hodlr_get_level",
            "hodlr_get_info", "hodlr_get_block", "hodlr_query", "hodlr_export_block", "hodlr_matvec",
            "hodlr_matvec_noalloc", "hodlr_matvec_batched", "hodlr_profile", "hodlr_profile_read",
-           "hodlr_destroy", "hodlr_status_string", "hodlr_last_error_message", "hodlr_last_error")
+           "hodlr_destroy", "hodlr_status_string", "hodlr_last_error_message", "hodlr_last_error",
+           "hodlr_build_kernel", "hodlr_get_norms")
+# kernel matrices the library evaluates itself (hodlr_build_kernel)
+KERNELS = {"gaussian": 0, "inv_dist": 1, "log": 2, "exp": 3, "signed_inv": 4}
 # entry points that return something other than hodlr_status
 _NON_STATUS = ("hodlr_depth_for_leaf", "hodlr_status_string", "hodlr_last_error_message", "hodlr_last_error")
 MAX_LEVELS = 24
@@ -58,6 +61,17 @@ class Info(C.Structure):
                 ("device", C.c_int32), ("eps", C.c_double), ("leaf_bytes", C.c_int64),
                 ("factor_bytes", C.c_int64), ("scale_bytes", C.c_int64),
                 ("device_bytes", C.c_int64)]
+
+
+class Kernel(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("a", C.c_double), ("diag_shift", C.c_double),
+                ("diag_value", C.c_double), ("diag_given", C.c_int32), ("reserved_", C.c_int32)]
+
+
+class BuildReport(C.Structure):
+    _fields_ = [("ms_norms", C.c_double), ("ms_factors", C.c_double), ("ms_total", C.c_double),
+                ("max_rank", C.c_int32), ("max_sketch", C.c_int32), ("sketch_rounds", C.c_int32),
+                ("exact_residual", C.c_int32)]
 
 
 class QueryInfo(C.Structure):
@@ -94,6 +108,8 @@ def lib():
         L.hodlr_get_info.argtypes = [vp, vp]
         L.hodlr_get_block.argtypes = [vp, i32, vp]
         L.hodlr_query.argtypes = [vp, vp, vp, vp]
+        L.hodlr_build_kernel.argtypes = [C.POINTER(vp), i64, i32, vp, vp, dp, C.c_uint64, i32, vp]
+        L.hodlr_get_norms.argtypes = [vp, vp]
         L.hodlr_export_block.argtypes = [vp, i32, vp, vp, vp, vp, i32]
         L.hodlr_matvec.argtypes = [vp, vp, i64, vp, i64, i32, i32, vp]
         L.hodlr_matvec_noalloc.argtypes = [vp, vp, i64, vp, i64, i32, i32, vp]
@@ -176,6 +192,13 @@ def colmajor_empty(n, nrhs, dtype, device):
 
 class Operator:
     """A HODLR operator held by the library (see ``include/hodlr.h``)."""
+
+    @classmethod
+    def _adopt(cls, handle, n, depth, device):
+        self = cls.__new__(cls)
+        self._h = handle
+        self.n, self.depth, self.nblocks, self.device = n, depth, (1 << (depth + 1)) - 2, device
+        return self
 
     def __init__(self, n, depth, leaves, U, V, device=0, leaf_bounds=None):
         self._h = C.c_void_p()
@@ -261,6 +284,13 @@ class Operator:
         d["ranks"] = rk[:self.nblocks]
         return d
 
+    def norms2(self):
+        """``hodlr_get_norms``: ||A||_F^2 and ||A_b||_F^2 of the original matrix
+        (operators made by ``build_kernel`` only)."""
+        out = np.zeros(1 + self.nblocks)
+        _check(lib().hodlr_get_norms(self._h, _ptr(out)))
+        return out
+
     def block(self, b):
         bi = BlockInfo()
         _check(lib().hodlr_get_block(self._h, b, C.byref(bi)))
@@ -340,6 +370,23 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+def build_kernel(points, depth, kind, a=0.0, diag_shift=0.0, diag_value=None, eps=1e-6, seed=0, device=0):
+    """``hodlr_build_kernel``: the eps-HODLR operator of the kernel matrix
+    k(p_i, p_j) (``kind`` a key of KERNELS) built on the GPU.  Returns the
+    Operator and the build report as a dict."""
+    P = np.ascontiguousarray(points, dtype=np.float64)
+    if P.ndim == 1:
+        P = P[:, None]
+    n, dim = P.shape
+    K = Kernel(KERNELS[kind] if isinstance(kind, str) else int(kind), dim, float(a), float(diag_shift),
+               0.0 if diag_value is None else float(diag_value), 0 if diag_value is None else 1, 0)
+    rep = BuildReport()
+    h = C.c_void_p()
+    _check(lib().hodlr_build_kernel(C.byref(h), n, depth, _ptr(P), C.byref(K), float(eps), C.c_uint64(seed), device,
+                                    C.byref(rep)))
+    return Operator._adopt(h, n, depth, device), {f: getattr(rep, f) for f, _ in BuildReport._fields_}
 
 
 def _xy_code(X):

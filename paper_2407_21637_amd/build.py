@@ -63,17 +63,20 @@ def _run_all(cmds):
 
 
 # device translation units of the library (compiled in parallel)
-DEVICE_TUS = ("kernels.hip", "kernels_lowp.hip", "kernels_batch.hip")
+DEVICE_TUS = ("kernels.hip", "kernels_lowp.hip", "kernels_batch.hip", "kernels_build.hip")
+HOST_TUS = ("host.cpp", "construct.cpp")
 
 
 def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     with tempfile.TemporaryDirectory(prefix="hodlr_build_") as tmp:
-        host_o = os.path.join(tmp, "host.o")
-        objs = [host_o]
-        cmds = [[hipcc, "-std=c++17", "-O2", "-fPIC", "-Wall", "-c", *DEFINES, *inc,
-                 os.path.join(CSRC, "host.cpp"), "-o", host_o]]
+        objs, cmds = [], []
+        for tu in HOST_TUS:
+            o = os.path.join(tmp, tu.replace(".cpp", ".o"))
+            objs.append(o)
+            cmds.append([hipcc, "-std=c++17", "-O2", "-fPIC", "-Wall", "-c", *DEFINES, *inc,
+                         os.path.join(CSRC, tu), "-o", o])
         for tu in DEVICE_TUS:
             o = os.path.join(tmp, tu.replace(".hip", ".o"))
             objs.append(o)

@@ -26,6 +26,7 @@
 
 #include "../../include/hodlr.h"
 #include "hodlr_internal.h"
+#include "host_internal.h"
 
 using namespace hodlr;
 
@@ -246,6 +247,11 @@ struct hodlr_op_s {
     std::vector<HBlock> blocks;
     std::vector<int32_t> rank;
     std::vector<std::vector<double>> U, V, D;   // fp64, column-major, ld = rows
+
+    // squared norms of the original matrix, when the operator was built from it
+    bool have_orig = false;
+    double orig_norm2_all = 0.0;
+    std::vector<double> orig_norm2;            // per block
 
     // assignment
     std::vector<int32_t> level_fmt;            // per level k-1
@@ -835,9 +841,16 @@ hodlr_status hodlr_assign_precision(hodlr_op op, double eps, const int32_t* allo
         for (int k = 0; k < depth; ++k)
             if (!(xi_in[k] >= 0.0) || std::isinf(xi_in[k]))
                 return fail(HODLR_E_ARG, "xi[%d] is negative, infinite or NaN", k);
-    // nrmAll, ||H_b||_F^2 and their per-level maxima
+    // nrmAll, ||H_b||_F^2 and their per-level maxima: given, the original
+    // matrix's (operators built by hodlr_build_kernel), or from the factors
+    std::vector<double> tmp_norms;
     double all = 0.0;
     std::vector<double> lvl(depth, 0.0), bn2(op->nb, 0.0);
+    if (!norms2 && op->have_orig) {
+        tmp_norms.push_back(op->orig_norm2_all);
+        tmp_norms.insert(tmp_norms.end(), op->orig_norm2.begin(), op->orig_norm2.end());
+        norms2 = tmp_norms.data();
+    }
     if (norms2) {
         all = norms2[0];
         for (int b = 0; b < op->nb; ++b) {
@@ -1903,8 +1916,31 @@ const char* hodlr_status_string(hodlr_status s) {
     return "HODLR_E_UNKNOWN";
 }
 
+hodlr_status hodlr_get_norms(hodlr_op op, double* norms2) {
+    if (!op || !norms2) return fail(HODLR_E_ARG, "NULL argument");
+    if (!op->have_orig) return fail(HODLR_E_STATE, "the operator carries no norms of an original matrix");
+    norms2[0] = op->orig_norm2_all;
+    std::memcpy(norms2 + 1, op->orig_norm2.data(), sizeof(double) * size_t(op->nb));
+    return ok();
+}
+
 const char* hodlr_last_error(void) { return g_last_error.c_str(); }
 
 const char* hodlr_last_error_message(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
+
+namespace hodlr {
+
+hodlr_status host_fail(hodlr_status s, const std::string& msg) {
+    if (s == HODLR_OK) return ok();
+    return fail(s, "%s", msg.c_str());
+}
+
+void attach_original_norms(hodlr_op op, double norm2_all, const double* norm2_blocks) {
+    op->have_orig = true;
+    op->orig_norm2_all = norm2_all;
+    op->orig_norm2.assign(norm2_blocks, norm2_blocks + op->nb);
+}
+
+}  // namespace hodlr
