@@ -17,6 +17,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from tests.parity_util import Case  # noqa: E402
+from oracle import bounds as BD  # noqa: E402
 from oracle import formats as F  # noqa: E402
 from oracle import lowp as LP  # noqa: E402
 from oracle import quantize as Q  # noqa: E402
@@ -214,3 +215,53 @@ def test_first_call_on_two_streams_at_once():
         torch.cuda.synchronize()
         assert torch.equal(Y1, want) and torch.equal(Y2, want), rep
         h.close()
+
+
+def _gpu_backward_errors(A, cfg, eps, X):
+    """eta = ||y - A x|| / (||A||_F ||x||) of the library's products of the
+    eps-HODLR operator of A (adaptive formats), per working precision,
+    averaged over the columns of X."""
+    from oracle import construct as OC
+    h = OC.construct(A, cfg.depth, eps)
+    lib = H.Operator(cfg.n, cfg.depth, h.leaves, h.U, h.V, device=0)
+    lib.assign_precision(eps, cfg.allowed, np.concatenate([[h.norm2_all], h.norm2_blocks]))
+    nA = np.sqrt(h.norm2_all)
+    out = {}
+    for w, dt in (("fp64", torch.float64), ("fp32", torch.float32), ("bf16", torch.bfloat16),
+                  ("fp16", torch.float16)):
+        Xw = X if w == "fp64" else F.round_rne(w, X)
+        Xd = H.colmajor_empty(cfg.n, X.shape[1], dt, DEV)
+        Xd.copy_(torch.from_numpy(np.asfortranarray(Xw)).to(dt))
+        Y = lib.matvec(Xd)
+        torch.cuda.synchronize()
+        Yh = Y.double().cpu().numpy()
+        out[w] = float(np.mean([np.linalg.norm(Yh[:, j] - A @ Xw[:, j]) / (nA * np.linalg.norm(Xw[:, j]))
+                                for j in range(X.shape[1])]))
+    lib.close()
+    return out
+
+
+@pytest.mark.parametrize("cfg", ["mat3", "mat1"])
+def test_working_precision_crossover_on_the_device(cfg):
+    """Sect. 4's matrix-vector experiment on the GPU path: with a working
+    precision u the backward error is the finite-precision one (well above
+    fp64's, at most u) while eps << u, and the approximation one once
+    eps >> u; fp64 always meets Thm. 3.5 (u = 2^-53 <= eps / n)."""
+    from hodlr_inputs import configs as CF
+    c = CF.get(cfg)
+    A = c.kernel.dense(c.points())
+    X = np.random.default_rng(0).uniform(-1, 1, (c.n, 3))
+    e = {}
+    for eps in (1e-8, 1e-6, 1e-4, 1e-3, 1e-2, 1e-1):
+        e[eps] = _gpu_backward_errors(A, c, eps, X)
+        _say(f"[crossover] {cfg} eps={eps:g}: " + ", ".join(f"{w} {v:.2e}" for w, v in e[eps].items()))
+        assert e[eps]["fp64"] <= BD.matvec_backward_bound(c.depth, eps)
+    for w in ("bf16", "fp16"):
+        u = F.fmt(w).u
+        assert e[1e-8][w] > 100 * e[1e-8]["fp64"]         # finite precision dominates
+        assert e[1e-8][w] <= u
+        assert e[1e-1][w] <= 1.1 * e[1e-1]["fp64"]       # approximation dominates
+    assert e[1e-3]["bf16"] > 2 * e[1e-3]["fp64"]          # eps = 1e-3 < u_bf16: still bf16's
+    assert e[1e-4]["fp16"] > 2 * e[1e-4]["fp64"]          # eps = 1e-4 < u_fp16: still fp16's
+    # fp32 working precision: its roundoff shows only below eps ~ 1e-7
+    assert e[1e-8]["fp32"] <= 2 * F.fmt("fp32").u and e[1e-2]["fp32"] <= 1.1 * e[1e-2]["fp64"]
