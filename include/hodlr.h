@@ -366,6 +366,54 @@ hodlr_status hodlr_matvec_batched(const hodlr_op* ops, int32_t count, const void
 hodlr_status hodlr_profile(hodlr_op op, int32_t capacity);
 hodlr_status hodlr_profile_read(hodlr_op op, double* ms_per_phase, int64_t* launches_per_phase);
 
+/* ---- LU factorization and solves (Sect. 3.4) ------------------------ */
+
+typedef struct {
+    double ms_factor;         /* the factorization on the host (image upload excluded) */
+    double norm_l;            /* ||L||_F and ||U||_F of the factors (exact, not formed) */
+    double norm_u;
+    int32_t max_rank;         /* widest off-diagonal generator met, updates included */
+    int32_t reserved_;
+} hodlr_lu_report;
+
+/* Factor the operator as stored, H = L U (Alg. "HODLR_LU"), and keep the
+ * factors with it.  The input is the mixed-precision representation the
+ * product uses: fp64 leaves and every generator decoded from its stored
+ * format.  Runs in fp64 on the host: leaves by LU without pivoting (unit
+ * lower L); for H = [[H11, U12 V12^T], [U21 V21^T, H22]] the factors of H11,
+ * then U's block (1,2) = (L11^-1 U12) V12^T and L's block (2,1) =
+ * U21 (U11^-T V21)^T, then the Schur complement H22 - L21 U12 as a low-rank
+ * update down H22's tree whose off-diagonal blocks are recompressed to the
+ * smallest rank with ||B~ - B^||_F <= eps ||B~||_F (the truncation
+ * assumption of Sect. 3.4; eps = 0 keeps every nonzero singular value), and
+ * the factors of it.  The backward error then obeys Cor. "LU of
+ * mixed-precision HODLR matrices": ||L U - H||_F <~ 2 (2^l - 1) eps ||H||_F
+ * + 11 (2^l - 1) eps ||L||_F ||U||_F (with the representation's own error
+ * against the original matrix added).  On a device handle the factors are
+ * also uploaded for hodlr_solve.  Reassigning formats (hodlr_assign_
+ * precision, hodlr_set_level_formats) or destroying the operator drops
+ * them.  E_UNSUPPORTED on a zero pivot (no LU without pivoting);
+ * E_ARG unless 0 <= eps < 1; report may be NULL. */
+hodlr_status hodlr_lu(hodlr_op op, double eps, hodlr_lu_report* report);
+
+/* X = U^-1 L^-1 B with the factors of hodlr_lu, on the GPU, on `stream`
+ * (stream-ordered like hodlr_matvec).  B, X: n x nrhs column-major device
+ * buffers, both HODLR_FP64 or both HODLR_FP32 (xy_dtype), leading
+ * dimensions ldb, ldx >= n; B may alias X when ldb == ldx.  The substitution
+ * runs in fp64: forward over the tree (each leaf by the inverse of its
+ * L factor, each node's L21 = U21 Y21^T applied as a rank-r update), then
+ * backward with U.  The operator owns an fp64 workspace of about
+ * 2 n nrhs doubles, grown (with a device synchronisation) when a call needs
+ * more: calls that overlap on one operator race on it.  E_STATE without
+ * factors or on a host-only handle. */
+hodlr_status hodlr_solve(hodlr_op op, const void* B, int64_t ldb, void* X, int64_t ldx, int32_t nrhs,
+                         int32_t xy_dtype, hipStream_t stream);
+
+/* The factors as dense n x n column-major matrices (L unit lower, U upper
+ * triangular), for checking; either pointer may be NULL.  E_STATE without
+ * factors. */
+hodlr_status hodlr_lu_dense(hodlr_op op, double* L, int64_t ldl, double* U, int64_t ldu);
+
 hodlr_status hodlr_destroy(hodlr_op op);
 
 const char* hodlr_status_string(hodlr_status s);

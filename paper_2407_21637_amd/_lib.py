@@ -34,7 +34,7 @@ EXPORTS = ("hodlr_depth_for_leaf", "hodlr_tree_bounds", "hodlr_tree_blocks", "ho
            "hodlr_get_info", "hodlr_get_block", "hodlr_query", "hodlr_export_block", "hodlr_matvec",
            "hodlr_matvec_noalloc", "hodlr_matvec_batched", "hodlr_profile", "hodlr_profile_read",
            "hodlr_destroy", "hodlr_status_string", "hodlr_last_error_message", "hodlr_last_error",
-           "hodlr_build_kernel", "hodlr_get_norms")
+           "hodlr_build_kernel", "hodlr_get_norms", "hodlr_lu", "hodlr_solve", "hodlr_lu_dense")
 # kernel matrices the library evaluates itself (hodlr_build_kernel)
 KERNELS = {"gaussian": 0, "inv_dist": 1, "log": 2, "exp": 3, "signed_inv": 4}
 # entry points that return something other than hodlr_status
@@ -74,6 +74,11 @@ class BuildReport(C.Structure):
                 ("exact_residual", C.c_int32)]
 
 
+class LuReport(C.Structure):
+    _fields_ = [("ms_factor", C.c_double), ("norm_l", C.c_double), ("norm_u", C.c_double),
+                ("max_rank", C.c_int32), ("reserved_", C.c_int32)]
+
+
 class QueryInfo(C.Structure):
     _fields_ = [("info", Info), ("level_dtype", C.c_int32 * MAX_LEVELS), ("insufficient", C.c_int32 * MAX_LEVELS),
                 ("xi", C.c_double * MAX_LEVELS), ("u_prime", C.c_double * MAX_LEVELS),
@@ -110,6 +115,9 @@ def lib():
         L.hodlr_query.argtypes = [vp, vp, vp, vp]
         L.hodlr_build_kernel.argtypes = [C.POINTER(vp), i64, i32, vp, vp, dp, C.c_uint64, i32, vp]
         L.hodlr_get_norms.argtypes = [vp, vp]
+        L.hodlr_lu.argtypes = [vp, dp, vp]
+        L.hodlr_solve.argtypes = [vp, vp, i64, vp, i64, i32, i32, vp]
+        L.hodlr_lu_dense.argtypes = [vp, vp, i64, vp, i64]
         L.hodlr_export_block.argtypes = [vp, i32, vp, vp, vp, vp, i32]
         L.hodlr_matvec.argtypes = [vp, vp, i64, vp, i64, i32, i32, vp]
         L.hodlr_matvec_noalloc.argtypes = [vp, vp, i64, vp, i64, i32, i32, vp]
@@ -344,6 +352,28 @@ class Operator:
         _check(lib().hodlr_matvec_noalloc(self._h, C.c_void_p(xp), ldx, C.c_void_p(yp), ldy, nrhs, code,
                                           _stream_ptr(stream)))
         return Y
+
+    def lu(self, eps=0.0):
+        """``hodlr_lu``: factor the stored operator, H = L U (Schur complements
+        truncated at eps); returns the report as a dict."""
+        rep = LuReport()
+        _check(lib().hodlr_lu(self._h, float(eps), C.byref(rep)))
+        return {f: getattr(rep, f) for f, _ in LuReport._fields_ if f != "reserved_"}
+
+    def solve(self, B, X=None, stream=None):
+        """``hodlr_solve``: X = U^-1 L^-1 B on the GPU for float64 / float32
+        torch tensors ((n,) or (n, nrhs) column-major); X allocated if None."""
+        bp, ldb, X, xp, ldx, nrhs, code = self._xy(B, X)
+        _check(lib().hodlr_solve(self._h, C.c_void_p(bp), ldb, C.c_void_p(xp), ldx, nrhs, code,
+                                 _stream_ptr(stream)))
+        return X
+
+    def lu_dense(self):
+        """``hodlr_lu_dense``: the factors as dense (L, U) numpy arrays."""
+        L = np.zeros((self.n, self.n), order="F")
+        U = np.zeros((self.n, self.n), order="F")
+        _check(lib().hodlr_lu_dense(self._h, _ptr(L), self.n, _ptr(U), self.n))
+        return L, U
 
     def profile(self, capacity):
         """Record per-phase event timings for the next ``capacity`` products."""

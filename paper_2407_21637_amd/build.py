@@ -63,8 +63,8 @@ def _run_all(cmds):
 
 
 # device translation units of the library (compiled in parallel)
-DEVICE_TUS = ("kernels.hip", "kernels_lowp.hip", "kernels_batch.hip", "kernels_build.hip")
-HOST_TUS = ("host.cpp", "construct.cpp")
+DEVICE_TUS = ("kernels.hip", "kernels_lowp.hip", "kernels_batch.hip", "kernels_build.hip", "kernels_lu.hip")
+HOST_TUS = ("host.cpp", "construct.cpp", "lu.cpp")
 
 
 def build(verbose: bool = False) -> str:

@@ -260,6 +260,9 @@ struct hodlr_op_s {
     std::vector<int32_t> insufficient;
     double eps = 0.0;
     bool acc_double = true;
+    // LU factors of the stored operator (hodlr_lu), owned through lu_free
+    void* lu = nullptr;
+    void (*lu_free)(void*) = nullptr;
     bool scale_cols = true;
 
     // padded layout
@@ -308,6 +311,12 @@ struct hodlr_op_s {
 };
 
 namespace {
+
+void drop_lu(hodlr_op_s* op) {
+    if (op->lu && op->lu_free) op->lu_free(op->lu);
+    op->lu = nullptr;
+    op->lu_free = nullptr;
+}
 
 int64_t node_of(const hodlr_op_s* op, int k, int64_t j, int64_t* b, int64_t* e) {
     const int64_t* lv = op->bounds.data() + ((int64_t(1) << k) - 1) + k;
@@ -935,6 +944,7 @@ hodlr_status hodlr_assign_precision(hodlr_op op, double eps, const int32_t* allo
     op->uprime = up;
     op->insufficient = bad;
     op->eps = eps;
+    drop_lu(op);                  // factors of the previous representation
     return ok();
 }
 
@@ -969,6 +979,7 @@ hodlr_status hodlr_set_level_precisions(hodlr_op op, const int32_t* per_level, u
     op->uprime.assign(op->depth, 0.0);
     op->insufficient.assign(op->depth, 0);
     op->eps = 0.0;
+    drop_lu(op);
     return ok();
 }
 
@@ -1898,6 +1909,7 @@ hodlr_status hodlr_destroy(hodlr_op op) {
         (void)hipDeviceSynchronize();
     }
     batch_forget(op->uid);
+    drop_lu(op);
     free_device(op);
     delete op;
     return ok();
@@ -1942,5 +1954,76 @@ void attach_original_norms(hodlr_op op, double norm2_all, const double* norm2_bl
     op->orig_norm2_all = norm2_all;
     op->orig_norm2.assign(norm2_blocks, norm2_blocks + op->nb);
 }
+
+}  // namespace hodlr
+
+namespace hodlr {
+
+namespace {
+// The value of a code of format f (the inverse of encode_rne).
+double decode_code(uint64_t code, int f) {
+    if (f == F64) {
+        double v;
+        std::memcpy(&v, &code, 8);
+        return v;
+    }
+    if (f == F32) {
+        const uint32_t c = uint32_t(code);
+        float v;
+        std::memcpy(&v, &c, 4);
+        return v;
+    }
+    const FmtInfo& F = kFmt[f];
+    const int nbits = 8 * fmt_bytes(f), mbits = F.t - 1;
+    const bool neg = (code >> (nbits - 1)) & 1;
+    const int ex = int((code >> mbits) & ((uint64_t(1) << F.ebits) - 1));
+    const double m = double(code & ((uint64_t(1) << mbits) - 1));
+    const double v = ex == 0 ? std::ldexp(m, 1 - F.bias - mbits) : std::ldexp(1.0 + std::ldexp(m, -mbits), ex - F.bias);
+    return neg ? -v : v;
+}
+}  // namespace
+
+hodlr_status stored_operator(hodlr_op op, StoredView* out) {
+    if (!op || !out) return fail(HODLR_E_ARG, "NULL argument");
+    out->n = op->n;
+    out->depth = op->depth;
+    out->bounds = op->bounds;
+    out->leaves = op->D;
+    out->U.assign(size_t(op->nb), {});
+    out->V.assign(size_t(op->nb), {});
+    out->rank = op->rank;
+    std::vector<hodlr_status> st(size_t(op->nb), HODLR_OK);
+    parallel_for(op->nb, [&](int64_t b) {
+        const HBlock& hb = op->blocks[size_t(b)];
+        const int f = op->block_fmt.empty() ? op->level_fmt[size_t(hb.level - 1)] : op->block_fmt[size_t(b)];
+        const int p = op->rank[size_t(b)];
+        for (int side = 0; side < 2; ++side) {
+            const std::vector<double>& Fm = side == 0 ? op->U[size_t(b)] : op->V[size_t(b)];
+            const int64_t rows = side == 0 ? hb.nrows : hb.ncols;
+            std::vector<double>& dst = side == 0 ? out->U[size_t(b)] : out->V[size_t(b)];
+            dst.assign(size_t(rows) * p, 0.0);
+            std::vector<int32_t> ex(size_t(std::max(p, 1)), 0);
+            const hodlr_status r = quantize_factor(Fm, rows, p, f, op->scale_cols, ex.data(),
+                                                   [&](int64_t i, int j, uint64_t code) {
+                                                       dst[size_t(j) * rows + i] =
+                                                           std::ldexp(decode_code(code, f), -ex[size_t(j)]);
+                                                   });
+            if (r != HODLR_OK) st[size_t(b)] = r;
+        }
+    });
+    for (hodlr_status r : st)
+        if (r != HODLR_OK) return r;
+    return HODLR_OK;
+}
+
+void* get_lu(hodlr_op op) { return op->lu; }
+
+void set_lu(hodlr_op op, void* lu, void (*lu_free)(void*)) {
+    drop_lu(op);
+    op->lu = lu;
+    op->lu_free = lu_free;
+}
+
+int op_device(hodlr_op op) { return op->device; }
 
 }  // namespace hodlr
