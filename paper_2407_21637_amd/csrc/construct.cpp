@@ -46,6 +46,7 @@
 #include <vector>
 
 #include "../../include/hodlr.h"
+#include "build_internal.h"
 #include "hodlr_internal.h"
 #include "host_internal.h"
 

@@ -28,7 +28,6 @@
 #pragma once
 
 #include <cstddef>
-#include <algorithm>
 #include <cstdint>
 
 namespace hodlr {
@@ -178,109 +177,6 @@ int scratch_address(int device, void** ptr);
 // Zero n int32 words at p on `stream` with a fill kernel (no memset node,
 // so the call may be captured into a graph).  Returns a hipError_t as int.
 int launch_zero_words(int32_t* p, int64_t n, void* stream);
-
-// ---------------------------------------------------------------------------
-// construction from a kernel matrix (hodlr_build_kernel, kernels_build.hip)
-// ---------------------------------------------------------------------------
-constexpr int kMaxSketch = 128;      // widest sketch (columns of Omega) of the range finder
-constexpr int kGramRows = 1024;      // rows of a partial Gram matrix
-constexpr int kBuildRows = 64;       // output rows of an on-the-fly product tile
-constexpr int kResidualRows = 32;    // rows of a residual tile
-
-struct BuildKernel {                 // A_ij = k(p_i, p_j) (+ diag_shift if i == j)
-    int32_t kind;                    // 0 exp(-r^2/a), 1 1/(r+a), 2 log(r+a), 3 exp(-r), 4 1/(x_i-x_j) (1D)
-    int32_t dim;                     // coordinates per point (1 or 2)
-    double a;
-    double diag_shift;
-    double diag_value;               // used at i == j when diag_given
-    int32_t diag_given;
-    int32_t pad_;
-};
-
-struct BuildTile {                   // rows [r0, r0+nr) x columns [c0, c0+nc) of A
-    int64_t r0, c0;
-    int32_t nr, nc;
-    int64_t out;                     // leaves: element offset of D_i
-};
-
-// One block's panel of a batched tall-skinny operation:
-//  * apply: Out (outer x s, at o_off) = B W (trans 0: outer = rows, inner =
-//    cols) or B^T W (trans 1: outer = cols, inner = rows), W (inner x s, at
-//    w_off), B the block whose first row and column are r0 and c0;
-//  * Omega: W (inner x s, at w_off) drawn for `block`;
-//  * Gram: A (outer x s, at o_off);
-//  * small product: C (outer x p, at c_off) = A (outer x s, at o_off) S
-//    (s x p, at w_off);
-//  * residual: Q (rows x s, at o_off), M^T (cols x s, at c_off).
-// Matrices are column-major with leading dimension = their row count.
-struct BuildPanel {
-    int64_t r0, c0;
-    int32_t outer, inner;
-    int32_t s, p;
-    int32_t trans, block;
-    int64_t w_off, o_off, c_off;
-};
-
-struct BuildItem {                   // a workgroup's part of a panel: rows from row0
-    int32_t panel;
-    int32_t row0;
-};
-
-// Launches on `stream`; each returns a hipError_t as int.
-int launch_build_norms(const BuildKernel& K, const double* P, const BuildTile* tiles, int ntiles, double* out,
-                       void* stream);
-int launch_build_omega(const BuildPanel* pans, int npan, uint64_t seed, double* W, void* stream);
-int launch_build_apply(const BuildKernel& K, const double* P, const BuildPanel* pans, const BuildItem* items,
-                       int nitems, const double* W, double* Out, void* stream);
-int launch_build_gram(const BuildPanel* pans, const BuildItem* items, int nitems, const double* A, double* out,
-                      void* stream);
-int launch_build_small_gemm(const BuildPanel* pans, const BuildItem* items, int nitems, const double* A,
-                            const double* S, double* C, void* stream);
-int launch_build_residual(const BuildKernel& K, const double* P, const BuildPanel* pans, const BuildItem* items,
-                          int nitems, const double* Q, const double* Mt, double* out, void* stream);
-int launch_build_leaves(const BuildKernel& K, const double* P, const BuildTile* leaves, int nleaves, double* D,
-                        void* stream);
-
-// ---------------------------------------------------------------------------
-// triangular solves with the LU factors (hodlr_solve, kernels_lu.hip)
-// ---------------------------------------------------------------------------
-// One step of forward or back substitution over the tree.  The solve keeps
-// two fp64 n x nrhs arrays: P (values still pending updates) and S (solved
-// values).
-//  * kind 0, a leaf: S[s0, s0+m) = M P[s0, s0+m), M the m x m inverse of the
-//    leaf's triangular factor at image offset a;
-//  * kind 1, a node: P[d0, d0+md) -= Bm (A^T S[s0, s0+m)), A (m x r) at
-//    offset a, Bm (md x r) at offset b.
-// Every matrix in the image is column-major with its row count as leading
-// dimension.
-struct LuStep {
-    int32_t kind;
-    int32_t m;
-    int32_t md;
-    int32_t r;
-    int64_t s0;
-    int64_t d0;
-    int64_t a;
-    int64_t b;
-};
-
-constexpr int kLuCols = 16;          // right-hand sides per workgroup of a solve step
-constexpr int kLuParts = 32;         // workgroups of a node step's reduction
-
-// Device memory of one solve with nrhs right-hand sides: P, S (n x nrhs
-// each), the reduction's partial sums (kLuParts x nrhs x rmax) and T
-// (nrhs x rmax), in doubles.
-inline int64_t lu_workspace_doubles(int64_t n, int nrhs, int rmax) {
-    return 2 * n * nrhs + int64_t(kLuParts + 1) * nrhs * std::max(rmax, 1);
-}
-
-// X = U^-1 L^-1 B on `stream`: B and X are fp64 (f64) or fp32, n x nrhs,
-// column-major; fwd and bwd (host arrays) the forward and backward steps;
-// img the device image of the factors; ws a device workspace of
-// lu_workspace_doubles(n, nrhs, rmax).  Returns a hipError_t as int.
-int launch_lu_solve(const double* img, const LuStep* fwd, int nfwd, const LuStep* bwd, int nbwd, int64_t n,
-                    const void* B, int64_t ldb, void* X, int64_t ldx, int nrhs, bool f64, int rmax, double* ws,
-                    void* stream);
 
 // ---------------------------------------------------------------------------
 // batched products: persistent launches over many operators

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "build_internal.h"
 #include "hodlr_internal.h"
 
 namespace hodlr {

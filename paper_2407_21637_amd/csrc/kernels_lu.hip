@@ -15,7 +15,7 @@
 
 #include <cstdint>
 
-#include "hodlr_internal.h"
+#include "lu_internal.h"
 
 namespace hodlr {
 namespace {

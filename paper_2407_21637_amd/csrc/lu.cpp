@@ -42,7 +42,7 @@
 #include <vector>
 
 #include "../../include/hodlr.h"
-#include "hodlr_internal.h"
+#include "lu_internal.h"
 #include "host_internal.h"
 
 using namespace hodlr;
