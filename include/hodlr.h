@@ -389,8 +389,9 @@ typedef struct {
  * the factors of it.  The backward error then obeys Cor. "LU of
  * mixed-precision HODLR matrices": ||L U - H||_F <~ 2 (2^l - 1) eps ||H||_F
  * + 11 (2^l - 1) eps ||L||_F ||U||_F (with the representation's own error
- * against the original matrix added).  On a device handle the factors are
- * also uploaded for hodlr_solve.  Reassigning formats (hodlr_assign_
+ * against the original matrix added).  On a device handle the inverse
+ * factors are also formed and uploaded for hodlr_solve (see there; about
+ * twice the device memory of the fp64 operator).  Reassigning formats (hodlr_assign_
  * precision, hodlr_set_level_formats) or destroying the operator drops
  * them.  E_UNSUPPORTED on a zero pivot (no LU without pivoting);
  * E_ARG unless 0 <= eps < 1; report may be NULL. */
@@ -399,13 +400,17 @@ hodlr_status hodlr_lu(hodlr_op op, double eps, hodlr_lu_report* report);
 /* X = U^-1 L^-1 B with the factors of hodlr_lu, on the GPU, on `stream`
  * (stream-ordered like hodlr_matvec).  B, X: n x nrhs column-major device
  * buffers, both HODLR_FP64 or both HODLR_FP32 (xy_dtype), leading
- * dimensions ldb, ldx >= n; B may alias X when ldb == ldx.  The substitution
- * runs in fp64: forward over the tree (each leaf by the inverse of its
- * L factor, each node's L21 = U21 Y21^T applied as a rank-r update), then
- * backward with U.  The operator owns an fp64 workspace of about
- * 2 n nrhs doubles, grown (with a device synchronisation) when a call needs
- * more: calls that overlap on one operator race on it.  E_STATE without
- * factors or on a host-only handle. */
+ * dimensions ldb, ldx >= n; B may alias X when ldb == ldx.  hodlr_lu forms
+ * L^-1 and U^-1 as HODLR matrices of the same tree and ranks (the inverse of
+ * a triangular HODLR matrix is one: L^-1's block (2,1) is
+ * (-L22^-1 U21)(L11^-T Y21)^T, U^-1's block (1,2) is
+ * (-U11^-1 X12)(U22^-T V12)^T, the leaves the inverses of the leaves'
+ * triangular factors, all formed in fp64), and the solve is two fp64
+ * products with fp64 accumulation, Z = L^-1 B then X = U^-1 Z (fp32 B is
+ * widened first and X rounded once).  The operator owns an fp64 workspace
+ * of 2 n nrhs doubles, grown (with a device synchronisation) when a call
+ * needs more: calls that overlap on one operator race on it.  E_STATE
+ * without factors or on a host-only handle. */
 hodlr_status hodlr_solve(hodlr_op op, const void* B, int64_t ldb, void* X, int64_t ldx, int32_t nrhs,
                          int32_t xy_dtype, hipStream_t stream);
 

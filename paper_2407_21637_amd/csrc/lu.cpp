@@ -20,13 +20,18 @@
 // performs no row exchanges.  Truncation: Householder QR of both factors
 // and a one-sided Jacobi SVD of the small core.
 //
-// The solve X = U^-1 L^-1 B runs on the GPU (kernels_lu.hip) from a device
-// image of the factors: per leaf the inverses of its triangular factors,
-// per internal node the generators of L's (2,1) and U's (1,2) blocks.
-// Forward substitution visits the tree left to right (leaf: W_i = L_i^-1
-// W_i; node, once its left subtree is done: W_2 -= U21 (Y21^T W_1)); back
-// substitution right to left (leaf: W_i = U_i^-1 W_i; node, once its right
-// subtree is done: W_1 -= X12 (V12^T W_2)).
+// The solve X = U^-1 L^-1 B runs on the GPU as two HODLR products.  The
+// inverse of a lower triangular HODLR matrix is lower triangular HODLR with
+// the same tree and ranks: for L = [[L11, 0], [U21 Y21^T, L22]],
+//   L^-1 = [[L11^-1, 0], [(-L22^-1 U21)(L11^-T Y21)^T, L22^-1]],
+// and for U = [[U11, X12 V12^T], [0, U22]],
+//   U^-1 = [[U11^-1, (-U11^-1 X12)(U22^-T V12)^T], [0, U22^-1]].
+// After the factorization the generators of both inverses are formed on the
+// host (triangular solves over the subtrees, in fp64) with the inverses of
+// the leaves' triangular factors as their leaves; each inverse becomes an
+// internal uniform-fp64 operator with fp64 accumulation (hodlr_create), and
+// hodlr_solve applies them with hodlr_matvec: every solve is then two
+// products on the product's kernels instead of a chain of dependent steps.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -35,10 +40,12 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <atomic>
 #include <future>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/hodlr.h"
@@ -310,11 +317,9 @@ struct Factors {
     std::vector<Mat> X12, Y21;              // per internal node: U's (1,2) = X12 V12^T, L's (2,1) = U21 Y21^T
     double eps = 0.0;
     int32_t max_rank = 0;
-    // device image for the solve
+    // the inverse factors as device operators, for the solve
     int device = -1;
-    void* d_img = nullptr;
-    std::vector<LuStep> fwd, bwd;
-    int rmax = 0;                           // widest node step
+    hodlr_op linv = nullptr, uinv = nullptr;
     std::mutex mu;                          // guards the solve workspace
     double* d_ws = nullptr;
     int64_t ws_doubles = 0;
@@ -322,11 +327,12 @@ struct Factors {
 
 void free_factors(void* p) {
     Factors* f = static_cast<Factors*>(p);
-    if (f->d_img || f->d_ws) {
+    if (f->linv) (void)hodlr_destroy(f->linv);
+    if (f->uinv) (void)hodlr_destroy(f->uinv);
+    if (f->d_ws) {
         (void)hipSetDevice(f->device);
         (void)hipDeviceSynchronize();
-        if (f->d_img) (void)hipFree(f->d_img);
-        if (f->d_ws) (void)hipFree(f->d_ws);
+        (void)hipFree(f->d_ws);
     }
     delete f;
 }
@@ -391,6 +397,48 @@ Mat solve_upper_t(const Factors& F, int k, int64_t j, const Mat& B) {
     Mat B2 = rows(B, m1, B.r - m1);
     sub_mul_nt(B2, F.V12[size_t(id)], mul_tn(X1, F.X12[size_t(id)]));   // B2 -= V12 (X12^T X1)
     return vcat(X1, solve_upper_t(F, k + 1, 2 * j + 1, B2));
+}
+
+Mat bwd_solve(const Mat& U, Mat B) {                 // U X = B, U upper
+    for (int64_t c = 0; c < B.c; ++c)
+        for (int64_t i = U.r - 1; i >= 0; --i) {
+            double s = B(i, c);
+            for (int64_t j = i + 1; j < U.r; ++j) s -= U(i, j) * B(j, c);
+            B(i, c) = s / U(i, i);
+        }
+    return B;
+}
+
+Mat bwd_solve_lt(const Mat& L, Mat B) {              // L^T X = B, L lower
+    for (int64_t c = 0; c < B.c; ++c)
+        for (int64_t i = L.r - 1; i >= 0; --i) {
+            double s = B(i, c);
+            for (int64_t j = i + 1; j < L.r; ++j) s -= L(j, i) * B(j, c);
+            B(i, c) = s / L(i, i);
+        }
+    return B;
+}
+
+// U X = B with the factored subtree at node (k, j): back substitution
+Mat solve_upper(const Factors& F, int k, int64_t j, const Mat& B) {
+    if (k == F.t.depth) return bwd_solve(F.Uf[size_t(j)], B);
+    const int id = F.t.id(k, j);
+    const int64_t m1 = F.t.sz[size_t(F.t.id(k + 1, 2 * j))];
+    Mat X2 = solve_upper(F, k + 1, 2 * j + 1, rows(B, m1, B.r - m1));
+    Mat B1 = rows(B, 0, m1);
+    sub_mul_nt(B1, F.X12[size_t(id)], mul_tn(X2, F.V12[size_t(id)]));   // B1 -= X12 (V12^T X2)
+    return vcat(solve_upper(F, k + 1, 2 * j, B1), X2);
+}
+
+// L^T X = B with the factored subtree at node (k, j): L^T's (1,2) block is Y21 U21^T
+Mat solve_lower_t(const Factors& F, int k, int64_t j, const Mat& B) {
+    if (k == F.t.depth) return bwd_solve_lt(F.Lf[size_t(j)], B);
+    const int id = F.t.id(k, j);
+    const int64_t m1 = F.t.sz[size_t(F.t.id(k + 1, 2 * j))];
+    Mat X2 = solve_lower_t(F, k + 1, 2 * j + 1, rows(B, m1, B.r - m1));
+    Mat B1 = rows(B, 0, m1);
+    sub_mul_nt(B1, F.Y21[size_t(id)], mul_tn(X2, F.U21[size_t(id)]));   // B1 -= Y21 (U21^T X2)
+    return vcat(solve_lower_t(F, k + 1, 2 * j, B1), X2);
 }
 
 // the working matrix of subtree (k, j) minus A B^T, blocks truncated
@@ -475,72 +523,70 @@ void lu_norms(const Factors& F, double* nl, double* nu) {
     *nu = std::sqrt(u2);
 }
 
-// the device image of the factors and the two step lists
-hodlr_status upload_factors(Factors& F) {
-    std::vector<double> img;
-    auto put = [&](const Mat& M) {
-        const int64_t off = int64_t(img.size());
-        img.insert(img.end(), M.a.begin(), M.a.end());
-        img.resize((img.size() + 31) / 32 * 32, 0.0);      // 256-byte aligned pieces
-        return off;
-    };
-    const int depth = F.t.depth;
-    std::vector<int64_t> linv(size_t(1) << depth), uinv(size_t(1) << depth);
-    for (int64_t j = 0; j < (int64_t(1) << depth); ++j) {
-        linv[size_t(j)] = put(invert_lower(F.Lf[size_t(j)]));
-        uinv[size_t(j)] = put(invert_upper(F.Uf[size_t(j)]));
-    }
-    const int ninner = (1 << depth) - 1;
-    std::vector<int64_t> oU21(size_t(std::max(ninner, 1))), oY21(oU21.size()), oX12(oU21.size()), oV12(oU21.size());
-    for (int id = 0; id < ninner; ++id) {
-        oU21[size_t(id)] = put(F.U21[size_t(id)]);
-        oY21[size_t(id)] = put(F.Y21[size_t(id)]);
-        oX12[size_t(id)] = put(F.X12[size_t(id)]);
-        oV12[size_t(id)] = put(F.V12[size_t(id)]);
-    }
-    // forward: left to right; after a node's left subtree, W2 -= U21 (Y21^T W1)
-    F.fwd.clear();
-    F.bwd.clear();
-    std::function<void(int, int64_t)> fw = [&](int k, int64_t j) {
-        const int id = F.t.id(k, j);
-        if (k == depth) {
-            F.fwd.push_back(LuStep{0, int32_t(F.t.sz[size_t(id)]), 0, 0, F.t.b0[size_t(id)], 0, linv[size_t(j)], 0});
-            return;
+// L^-1 and U^-1 as device operators (uniform fp64, fp64 accumulation)
+hodlr_status make_inverses(Factors& F) {
+    const Tree& t = F.t;
+    const int depth = t.depth, nl = 1 << depth, ninner = nl - 1;
+    std::vector<Mat> li(static_cast<size_t>(nl)), ui(static_cast<size_t>(nl));
+    std::vector<Mat> lu_(size_t(std::max(ninner, 1))), lv_(lu_.size()), uu_(lu_.size()), uv_(lu_.size());
+    // independent tasks: the leaves' inverses and each node's four generators
+    const int ntasks = nl + ninner;
+    std::atomic<int> next{0};
+    auto work = [&] {
+        for (int q = next++; q < ntasks; q = next++) {
+            if (q < nl) {
+                li[size_t(q)] = invert_lower(F.Lf[size_t(q)]);
+                ui[size_t(q)] = invert_upper(F.Uf[size_t(q)]);
+                continue;
+            }
+            const int id = q - nl;
+            int k = 0;
+            while (((1 << (k + 1)) - 1) <= id) ++k;
+            const int64_t j = id - ((int64_t(1) << k) - 1);
+            lu_[size_t(id)] = scaled(solve_lower(F, k + 1, 2 * j + 1, F.U21[size_t(id)]), -1.0);
+            lv_[size_t(id)] = solve_lower_t(F, k + 1, 2 * j, F.Y21[size_t(id)]);
+            uu_[size_t(id)] = scaled(solve_upper(F, k + 1, 2 * j, F.X12[size_t(id)]), -1.0);
+            uv_[size_t(id)] = solve_upper_t(F, k + 1, 2 * j + 1, F.V12[size_t(id)]);
         }
-        fw(k + 1, 2 * j);
-        const int c1 = F.t.id(k + 1, 2 * j), c2 = F.t.id(k + 1, 2 * j + 1);
-        F.fwd.push_back(LuStep{1, int32_t(F.t.sz[size_t(c1)]), int32_t(F.t.sz[size_t(c2)]), int32_t(F.Y21[size_t(id)].c),
-                               F.t.b0[size_t(c1)], F.t.b0[size_t(c2)], oY21[size_t(id)], oU21[size_t(id)]});
-        fw(k + 1, 2 * j + 1);
     };
-    // backward: right to left; after a node's right subtree, W1 -= X12 (V12^T W2)
-    std::function<void(int, int64_t)> bw = [&](int k, int64_t j) {
-        const int id = F.t.id(k, j);
-        if (k == depth) {
-            F.bwd.push_back(LuStep{0, int32_t(F.t.sz[size_t(id)]), 0, 0, F.t.b0[size_t(id)], 0, uinv[size_t(j)], 0});
-            return;
-        }
-        bw(k + 1, 2 * j + 1);
-        const int c1 = F.t.id(k + 1, 2 * j), c2 = F.t.id(k + 1, 2 * j + 1);
-        F.bwd.push_back(LuStep{1, int32_t(F.t.sz[size_t(c2)]), int32_t(F.t.sz[size_t(c1)]), int32_t(F.V12[size_t(id)].c),
-                               F.t.b0[size_t(c2)], F.t.b0[size_t(c1)], oV12[size_t(id)], oX12[size_t(id)]});
-        bw(k + 1, 2 * j);
-    };
-    fw(0, 0);
-    bw(0, 0);
-    F.rmax = 0;
-    for (const LuStep& x : F.fwd) F.rmax = std::max(F.rmax, int(x.r));
-    for (const LuStep& x : F.bwd) F.rmax = std::max(F.rmax, int(x.r));
-    hipError_t e = hipSetDevice(F.device);
-    if (e == hipSuccess) e = hipMalloc(&F.d_img, std::max<size_t>(img.size(), 1) * 8);
-    if (e != hipSuccess) {
-        F.d_img = nullptr;
-        (void)hipGetLastError();
-        return host_fail(HODLR_E_NOMEM, "device image of the LU factors");
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned i = 1; i < nth; ++i) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
+    // the two operators in canonical block order: block (k, j) has rows node j, columns node j^1;
+    // j even is the upper block of node (k-1, j/2), j odd the lower one
+    const int nb = (1 << (depth + 1)) - 2;
+    std::vector<int64_t> lb(size_t(nl) + 1);
+    for (int j = 0; j < nl; ++j) lb[size_t(j)] = t.b0[size_t(t.id(depth, j))];
+    lb[size_t(nl)] = F.n;
+    std::vector<const double*> lp(static_cast<size_t>(nl)), up(static_cast<size_t>(nl));
+    std::vector<int64_t> ld(static_cast<size_t>(nl));
+    for (int j = 0; j < nl; ++j) {
+        lp[size_t(j)] = li[size_t(j)].a.data();
+        up[size_t(j)] = ui[size_t(j)].a.data();
+        ld[size_t(j)] = std::max<int64_t>(1, li[size_t(j)].r);
     }
-    e = hipMemcpy(F.d_img, img.data(), img.size() * 8, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return host_fail(HODLR_E_DEVICE, std::string("uploading the LU factors: ") + hipGetErrorString(e));
-    return HODLR_OK;
+    std::vector<hodlr_lowrank> bl(size_t(std::max(nb, 1))), bu(bl.size());
+    for (int k = 1; k <= depth; ++k)
+        for (int64_t j = 0; j < (int64_t(1) << k); ++j) {
+            const int b = (1 << k) - 2 + int(j), parent = t.id(k - 1, j / 2);
+            const int64_t rr = std::max<int64_t>(1, t.sz[size_t(t.id(k, j))]);
+            const int64_t cc = std::max<int64_t>(1, t.sz[size_t(t.id(k, j ^ 1))]);
+            hodlr_lowrank none{0, nullptr, rr, nullptr, cc};
+            if ((j & 1) == 0) {          // upper: zero in L^-1
+                const Mat &Ug = uu_[size_t(parent)], &Vg = uv_[size_t(parent)];
+                bl[size_t(b)] = none;
+                bu[size_t(b)] = hodlr_lowrank{int32_t(Ug.c), Ug.a.data(), rr, Vg.a.data(), cc};
+            } else {                     // lower: zero in U^-1
+                const Mat &Ug = lu_[size_t(parent)], &Vg = lv_[size_t(parent)];
+                bl[size_t(b)] = hodlr_lowrank{int32_t(Ug.c), Ug.a.data(), rr, Vg.a.data(), cc};
+                bu[size_t(b)] = none;
+            }
+        }
+    hodlr_status r = hodlr_create(&F.linv, F.n, depth, lb.data(), lp.data(), ld.data(), bl.data(), F.device);
+    if (r == HODLR_OK) r = hodlr_create(&F.uinv, F.n, depth, lb.data(), up.data(), ld.data(), bu.data(), F.device);
+    return r;
 }
 
 }  // namespace
@@ -602,7 +648,11 @@ extern "C" hodlr_status hodlr_lu(hodlr_op op, double eps, hodlr_lu_report* repor
     if (!factor(*F, 0, 0))
         return host_fail(HODLR_E_UNSUPPORTED, "a zero pivot in a leaf: LU without pivoting does not exist");
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    if (F->device >= 0 && (r = upload_factors(*F)) != HODLR_OK) return r;
+    if (F->device >= 0 && (r = make_inverses(*F)) != HODLR_OK) {
+        const std::string msg = hodlr_last_error_message();
+        free_factors(F.release());
+        return host_fail(r, "the inverse factors as device operators: " + msg);
+    }
     if (report) {
         report->ms_factor = ms;
         lu_norms(*F, &report->norm_l, &report->norm_u);
@@ -667,7 +717,7 @@ extern "C" hodlr_status hodlr_solve(hodlr_op op, const void* B, int64_t ldb, voi
     if (!op) return host_fail(HODLR_E_ARG, "op is NULL");
     Factors* F = static_cast<Factors*>(get_lu(op));
     if (!F) return host_fail(HODLR_E_STATE, "no LU factors: call hodlr_lu first");
-    if (F->device < 0) return host_fail(HODLR_E_STATE, "host-only handle: no solve");
+    if (F->device < 0 || !F->linv) return host_fail(HODLR_E_STATE, "host-only handle: no solve");
     if (nrhs < 1) return host_fail(HODLR_E_ARG, "nrhs must be >= 1");
     if (xy_dtype != HODLR_FP64 && xy_dtype != HODLR_FP32)
         return host_fail(HODLR_E_UNSUPPORTED, "hodlr_solve takes HODLR_FP64 or HODLR_FP32 B and X");
@@ -676,7 +726,7 @@ extern "C" hodlr_status hodlr_solve(hodlr_op op, const void* B, int64_t ldb, voi
     hipError_t e = hipSetDevice(F->device);
     if (e != hipSuccess) return host_fail(HODLR_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
     std::lock_guard<std::mutex> lk(F->mu);
-    const int64_t need = lu_workspace_doubles(F->n, nrhs, F->rmax);
+    const int64_t need = 2 * F->n * int64_t(nrhs);
     if (need > F->ws_doubles) {
         if (F->d_ws) {                       // earlier solves may still read it
             (void)hipDeviceSynchronize();
@@ -692,9 +742,24 @@ extern "C" hodlr_status hodlr_solve(hodlr_op op, const void* B, int64_t ldb, voi
         F->d_ws = static_cast<double*>(p);
         F->ws_doubles = need;
     }
-    const int he = launch_lu_solve(static_cast<const double*>(F->d_img), F->fwd.data(), int(F->fwd.size()),
-                                   F->bwd.data(), int(F->bwd.size()), F->n, B, ldb, X, ldx, nrhs,
-                                   xy_dtype == HODLR_FP64, F->rmax, F->d_ws, static_cast<void*>(stream));
-    if (he != 0) return host_fail(HODLR_E_DEVICE, std::string("solve: ") + hipGetErrorString(hipError_t(he)));
+    // Z = L^-1 B and X = U^-1 Z in fp64 (fp32 B widened first, X rounded once at the end)
+    double* W0 = F->d_ws;
+    double* W1 = F->d_ws + F->n * nrhs;
+    const bool f64 = xy_dtype == HODLR_FP64;
+    hodlr_status r;
+    if (f64) {
+        r = hodlr_matvec(F->linv, B, ldb, W0, F->n, nrhs, HODLR_FP64, stream);
+        if (r == HODLR_OK) r = hodlr_matvec(F->uinv, W0, F->n, X, ldx, nrhs, HODLR_FP64, stream);
+    } else {
+        int he = launch_lu_convert(B, ldb, false, W1, F->n, true, F->n, nrhs, static_cast<void*>(stream));
+        if (he != 0) return host_fail(HODLR_E_DEVICE, std::string("solve: ") + hipGetErrorString(hipError_t(he)));
+        r = hodlr_matvec(F->linv, W1, F->n, W0, F->n, nrhs, HODLR_FP64, stream);
+        if (r == HODLR_OK) r = hodlr_matvec(F->uinv, W0, F->n, W1, F->n, nrhs, HODLR_FP64, stream);
+        if (r == HODLR_OK) {
+            he = launch_lu_convert(W1, F->n, true, X, ldx, false, F->n, nrhs, static_cast<void*>(stream));
+            if (he != 0) return host_fail(HODLR_E_DEVICE, std::string("solve: ") + hipGetErrorString(hipError_t(he)));
+        }
+    }
+    if (r != HODLR_OK) return host_fail(r, std::string("solve: ") + hodlr_last_error_message());
     return host_fail(HODLR_OK, "");
 }
