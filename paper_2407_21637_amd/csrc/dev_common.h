@@ -140,6 +140,110 @@ struct Codec<E5M2> {
 };
 
 // ---------------------------------------------------------------------------
+// loads whose use comes later
+// ---------------------------------------------------------------------------
+// A load through a global-address-space pointer: the generic pointers in the
+// kernels' parameter structs would otherwise become flat loads, which also
+// wait on the LDS counter.
+template <typename T>
+__device__ __forceinline__ T gload(const void* p) {
+    return *(const __attribute__((address_space(1))) T*)(p);
+}
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));   // plain vector types for gload
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// N consecutive codes of format F as raw bits.  The caller loads them from
+// an address it has clamped into the buffer, with no branch around the
+// load, and decodes (and masks) them after all the loads it has in flight
+// are issued: a load inside a branch whose value is decoded inside the
+// same branch makes the compiler wait for that load before issuing the
+// next one.
+template <int F, int N>
+struct RawCodes {
+    static constexpr int kBytes = N * Codec<F>::kBytes;
+    static constexpr int kWords = kBytes < 4 ? 1 : kBytes / 4;
+    uint32_t w[kWords];
+
+    __device__ __forceinline__ void load(const uint8_t* p) {
+        if constexpr (kBytes == 1) {
+            w[0] = gload<uint8_t>(p);
+        } else if constexpr (kBytes == 2) {
+            w[0] = gload<uint16_t>(p);
+        } else if constexpr (kBytes == 4) {
+            w[0] = gload<uint32_t>(p);
+        } else if constexpr (kBytes == 8) {
+            const u32x2 a = gload<u32x2>(p);
+            w[0] = a.x;
+            w[1] = a.y;
+        } else {
+#pragma unroll
+            for (int i = 0; i < kBytes / 16; ++i) {
+                const u32x4 a = gload<u32x4>(p + 16 * i);
+                w[4 * i] = a.x;
+                w[4 * i + 1] = a.y;
+                w[4 * i + 2] = a.z;
+                w[4 * i + 3] = a.w;
+            }
+        }
+    }
+
+    // the values Codec<F>::load would give; zero where !keep
+    template <typename CT>
+    __device__ __forceinline__ void decode(CT v[N], bool keep) const {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            CT x;
+            if constexpr (F == F64) {
+                x = CT(__builtin_bit_cast(double, uint64_t(w[2 * i]) | (uint64_t(w[2 * i + 1]) << 32)));
+            } else if constexpr (F == F32) {
+                x = CT(__uint_as_float(w[i]));
+            } else if constexpr (F == BF16) {
+                x = CT(__uint_as_float(((w[i / 2] >> (16 * (i & 1))) & 0xffffu) << 16));
+            } else if constexpr (F == F16) {
+                x = CT(half_bits_to_float((w[i / 2] >> (16 * (i & 1))) & 0xffffu));
+            } else if constexpr (F == E4M3) {
+                x = CT(e4m3_scaled(w[i / 4] >> (8 * (i & 3))));
+            } else {
+                x = CT(e5m2(w[i / 4] >> (8 * (i & 3))));
+            }
+            v[i] = keep ? x : CT(0);
+        }
+    }
+};
+
+// Codes of format F read as CT with no decode (fp64 as fp64, fp32 as
+// fp32): these keep the plain conditional loads, whose values the compiler
+// leaves in flight; every other pairing takes the RawCodes pattern.
+template <int F, typename CT>
+constexpr bool direct_codes() {
+    return (F == F64 && sizeof(CT) == 8) || (F == F32 && sizeof(CT) == 4);
+}
+
+// N consecutive values of a right-hand side (fp32 or fp64), loaded as
+// RawCodes are and converted later.
+template <typename XT, int N>
+struct RawX {
+    XT v[N];
+    __device__ __forceinline__ void load(const XT* p) {
+        if constexpr (sizeof(XT) * N % 16 == 0) {
+#pragma unroll
+            for (int i = 0; i < int(sizeof(XT)) * N / 16; ++i) {
+                const u32x4 a = gload<u32x4>(reinterpret_cast<const uint8_t*>(p) + 16 * i);
+                __builtin_memcpy(reinterpret_cast<uint8_t*>(v) + 16 * i, &a, 16);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] = gload<XT>(p + i);
+        }
+    }
+    template <typename CT>
+    __device__ __forceinline__ void convert(CT out[N], bool keep) const {
+#pragma unroll
+        for (int i = 0; i < N; ++i) out[i] = keep ? CT(v[i]) : CT(0);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // wave64 sum; the total ends in lane 63
 // ---------------------------------------------------------------------------
 template <int CTRL, int ROWMASK>

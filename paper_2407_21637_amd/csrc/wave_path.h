@@ -46,23 +46,60 @@ __device__ void contract_item(const KParams& kp, const CItem& it, const BlockDes
             for (int s0 = 0; s0 < nslab; s0 += GS / 4) {            // slab groups of GS/4
                 CT xr[GS / 4][4][RG];
                 CT v[GS / 4][CJ][4];
+                if constexpr (direct_codes<F, CT>() && sizeof(XT) == sizeof(CT)) {
 #pragma unroll
-                for (int q = 0; q < GS / 4; ++q) {
-                    const int row = (s0 + q) * 256 + 4 * lane;
-                    const bool ok = s0 + q < nslab && row < it.nr;
+                    for (int q = 0; q < GS / 4; ++q) {
+                        const int row = (s0 + q) * 256 + 4 * lane;
+                        const bool ok = s0 + q < nslab && row < it.nr;
 #pragma unroll
-                    for (int c = 0; c < CJ; ++c) {
-                        if (ok && j0 + c < p)
-                            Codec<F>::template load<4, CT>(Vp + (int64_t(j0 + c) * ld + row) * S, v[q][c]);
-                        else
-                            v[q][c][0] = v[q][c][1] = v[q][c][2] = v[q][c][3] = CT(0);
+                        for (int c = 0; c < CJ; ++c) {
+                            if (ok && j0 + c < p)
+                                Codec<F>::template load<4, CT>(Vp + (int64_t(j0 + c) * ld + row) * S, v[q][c]);
+                            else
+                                v[q][c][0] = v[q][c][1] = v[q][c][2] = v[q][c][3] = CT(0);
+                        }
+#pragma unroll
+                        for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                xr[q][i][rg] = (ok && row + i < it.nr && rb + rg < nrhs)
+                                                   ? CT(X[xrow0 + row + i + ldx * (rb + rg)]) : CT(0);
+                    }
+                } else {
+                    // codes or X that need decoding: all loads of the slab
+                    // group first, from addresses clamped into the item (rank
+                    // -> j0 < p, row -> 0, column -> 0), then decoded and masked
+                    RawCodes<F, 4> rv[GS / 4][CJ];
+                    RawX<XT, 1> rx[GS / 4][4][RG];
+#pragma unroll
+                    for (int q = 0; q < GS / 4; ++q) {
+                        const int row = (s0 + q) * 256 + 4 * lane;
+                        const bool ok = s0 + q < nslab && row < it.nr;
+#pragma unroll
+                        for (int c = 0; c < CJ; ++c)
+                            rv[q][c].load(Vp + (int64_t(j0 + c < p ? j0 + c : j0) * ld + (ok ? row : 0)) * S);
+#pragma unroll
+                        for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                const bool okx = ok && row + i < it.nr;
+                                rx[q][i][rg].load(X + xrow0 + (okx ? row + i : 0) +
+                                                  ldx * (rb + rg < nrhs ? rb + rg : 0));
+                            }
                     }
 #pragma unroll
-                    for (int rg = 0; rg < RG; ++rg)
+                    for (int q = 0; q < GS / 4; ++q) {
+                        const int row = (s0 + q) * 256 + 4 * lane;
+                        const bool ok = s0 + q < nslab && row < it.nr;
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            xr[q][i][rg] = (ok && row + i < it.nr && rb + rg < nrhs)
-                                               ? CT(X[xrow0 + row + i + ldx * (rb + rg)]) : CT(0);
+                        for (int c = 0; c < CJ; ++c) rv[q][c].template decode<CT>(v[q][c], ok && j0 + c < p);
+#pragma unroll
+                        for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                rx[q][i][rg].template convert<CT>(&xr[q][i][rg],
+                                                                  ok && row + i < it.nr && rb + rg < nrhs);
+                    }
                 }
 #pragma unroll
                 for (int q = 0; q < GS / 4; ++q)
@@ -265,15 +302,27 @@ __device__ __forceinline__ void expand_unit(const KParams& kp, const BlockDesc& 
     constexpr int S = Codec<F>::kBytes;
     constexpr int UN = F == F64 ? kUnroll / 2 : kUnroll;          // columns per unit (= unit_cols(F))
     const int p = bd.rank;
-    const uint8_t* Up = kp.fac + bd.u_off + (int64_t(chunk0) * p + rin) * S;
     CT u[UN][RPL];
+    if constexpr (direct_codes<F, CT>()) {
+        const uint8_t* Up = kp.fac + bd.u_off + (int64_t(chunk0) * p + rin) * S;
 #pragma unroll
-    for (int q = 0; q < UN; ++q) {
-        if (act && j0 + q < p)
-            Codec<F>::template load<RPL, CT>(Up + int64_t(j0 + q) * ld * S, u[q]);
-        else
+        for (int q = 0; q < UN; ++q) {
+            if (act && j0 + q < p)
+                Codec<F>::template load<RPL, CT>(Up + int64_t(j0 + q) * ld * S, u[q]);
+            else
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) u[q][i] = CT(0);
+                for (int i = 0; i < RPL; ++i) u[q][i] = CT(0);
+        }
+    } else {
+        // codes that need decoding: every column's codes are loaded before
+        // any is decoded, from addresses clamped into the chunk (rank -> j0
+        // < p, inactive lanes -> row 0)
+        const uint8_t* Up = kp.fac + bd.u_off + (int64_t(chunk0) * p + (act ? rin : 0)) * S;
+        RawCodes<F, RPL> ru[UN];
+#pragma unroll
+        for (int q = 0; q < UN; ++q) ru[q].load(Up + int64_t(j0 + q < p ? j0 + q : j0) * ld * S);
+#pragma unroll
+        for (int q = 0; q < UN; ++q) ru[q].template decode<CT>(u[q], act && j0 + q < p);
     }
     CT lacc[RPL][RG];
 #pragma unroll

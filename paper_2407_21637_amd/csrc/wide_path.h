@@ -121,23 +121,48 @@ __device__ void contract_item_w(const KParams& kp, const CItem& it, const BlockD
             const int row = st * kStep + g * kKL;       // nr and row are multiples of 8
             const bool ok = row < it.nr;
             CT a[PG][kKL], b[NT][kKL];
+            if constexpr (direct_codes<F, CT>()) {
 #pragma unroll
-            for (int pg = 0; pg < PG; ++pg) {
-                const int j = j0 + 16 * pg + li;
-                if (ok && j < p)
-                    load_codes8<F, CT>(Vp + (int64_t(j) * ld + row) * S, a[pg]);
-                else
+                for (int pg = 0; pg < PG; ++pg) {
+                    const int j = j0 + 16 * pg + li;
+                    if (ok && j < p)
+                        load_codes8<F, CT>(Vp + (int64_t(j) * ld + row) * S, a[pg]);
+                    else
 #pragma unroll
-                    for (int q = 0; q < kKL; ++q) a[pg][q] = CT(0);
+                        for (int q = 0; q < kKL; ++q) a[pg][q] = CT(0);
+                }
+            } else {
+                // codes that need decoding: all loads first, from clamped
+                // addresses (rank -> j0, row -> 0), then decoded and masked
+                RawCodes<F, kKL> rv[PG];
+#pragma unroll
+                for (int pg = 0; pg < PG; ++pg) {
+                    const int j = j0 + 16 * pg + li;
+                    rv[pg].load(Vp + (int64_t(j < p ? j : j0) * ld + (ok ? row : 0)) * S);
+                }
+#pragma unroll
+                for (int pg = 0; pg < PG; ++pg) rv[pg].template decode<CT>(a[pg], ok && j0 + 16 * pg + li < p);
             }
+            if constexpr (sizeof(XT) == sizeof(CT)) {
 #pragma unroll
-            for (int ct = 0; ct < NT; ++ct) {
-                const int c = c0 + 16 * ct + li;
-                if (ok && c < nrhs)
-                    load_x8<XT, CT>(Xr + row + ldx * c, b[ct]);
-                else
+                for (int ct = 0; ct < NT; ++ct) {
+                    const int c = c0 + 16 * ct + li;
+                    if (ok && c < nrhs)
+                        load_x8<XT, CT>(Xr + row + ldx * c, b[ct]);
+                    else
 #pragma unroll
-                    for (int q = 0; q < kKL; ++q) b[ct][q] = CT(0);
+                        for (int q = 0; q < kKL; ++q) b[ct][q] = CT(0);
+                }
+            } else {
+                // X converted to CT: loaded first (column -> c0, row -> 0), converted after
+                RawX<XT, kKL> rx[NT];
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct) {
+                    const int c = c0 + 16 * ct + li;
+                    rx[ct].load(Xr + (ok ? row : 0) + ldx * (c < nrhs ? c : c0));
+                }
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct) rx[ct].template convert<CT>(b[ct], ok && c0 + 16 * ct + li < nrhs);
             }
 #pragma unroll
             for (int q = 0; q < kKL; ++q)
@@ -280,15 +305,36 @@ __device__ void expand_level_w(const KParams& kp, const BlockDesc& bd, int chunk
             const int left = crows - j0 < 4 * QG ? crows - j0 : 4 * QG;
             const int qn = (left + 3) >> 2;             // MFMA groups holding some rank < p
             CT a0[QG], a1[QG];
+            if constexpr (direct_codes<F, CT>()) {
 #pragma unroll
-            for (int q = 0; q < QG; ++q) {
-                const int jr = j0 + 4 * q + g;          // rank within the staged rows
-                a0[q] = CT(0);
-                a1[q] = CT(0);
-                if (q < qn && jr < crows) {
-                    const uint8_t* col = Up + int64_t(cr0 + jr) * ld * S;
-                    if (act0) Codec<F>::template load<1, CT>(col + int64_t(r0) * S, &a0[q]);
-                    if (act1) Codec<F>::template load<1, CT>(col + int64_t(r1) * S, &a1[q]);
+                for (int q = 0; q < QG; ++q) {
+                    const int jr = j0 + 4 * q + g;      // rank within the staged rows
+                    a0[q] = CT(0);
+                    a1[q] = CT(0);
+                    if (q < qn && jr < crows) {
+                        const uint8_t* col = Up + int64_t(cr0 + jr) * ld * S;
+                        if (act0) Codec<F>::template load<1, CT>(col + int64_t(r0) * S, &a0[q]);
+                        if (act1) Codec<F>::template load<1, CT>(col + int64_t(r1) * S, &a1[q]);
+                    }
+                }
+            } else {
+                // codes that need decoding: every group's codes are loaded
+                // before any is decoded, from addresses clamped into the
+                // panel (rank -> the chunk's first staged rank, inactive
+                // rows -> row 0), and masked when decoded
+                RawCodes<F, 1> u0[QG], u1[QG];
+#pragma unroll
+                for (int q = 0; q < QG; ++q) {
+                    const int jr = j0 + 4 * q + g;
+                    const uint8_t* col = Up + int64_t(cr0 + (jr < crows ? jr : 0)) * ld * S;
+                    u0[q].load(col + int64_t(act0 ? r0 : 0) * S);
+                    u1[q].load(col + int64_t(act1 ? r1 : 0) * S);
+                }
+#pragma unroll
+                for (int q = 0; q < QG; ++q) {
+                    const bool okr = q < qn && j0 + 4 * q + g < crows;
+                    u0[q].template decode<CT>(&a0[q], okr && act0);
+                    u1[q].template decode<CT>(&a1[q], okr && act1);
                 }
             }
 #pragma unroll
