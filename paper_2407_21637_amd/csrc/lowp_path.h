@@ -47,20 +47,10 @@ __device__ __forceinline__ typename LpMfma<W>::v8 load_w8(const W* p) {
     return *reinterpret_cast<const V8*>(p);
 }
 
-// eight stored codes of one rank column (consecutive rows), rounded to W
-// (fp64 codes are rounded to W directly, the others are exact in fp32 first)
+// the type a stored code is decoded to before it is rounded to W (fp64
+// codes are rounded to W directly, the others are exact in fp32 first)
 template <int F>
 using CodeT = typename std::conditional<F == F64, double, float>::type;
-
-template <int F, typename W>
-__device__ __forceinline__ typename LpMfma<W>::v8 codes_to_w8(const uint8_t* p) {
-    CodeT<F> v[kKL];
-    load_codes8<F, CodeT<F>>(p, v);
-    typename LpMfma<W>::v8 r;
-#pragma unroll
-    for (int q = 0; q < kKL; ++q) r[q] = W(v[q]);
-    return r;
-}
 
 // ---------------------------------------------------------------------------
 // contraction: partial sums of V_b^T X per item, on the matrix cores
@@ -95,7 +85,11 @@ __device__ void contract_item_lp(const KParams& kp, const CItem& it, const Block
         // two of the wave's steps per pass, both loaded before either is multiplied (the
         // accumulation order, step st then st + kWaves, is that of one step per pass)
         for (int st = wave; st < nstep; st += 2 * kWaves) {
+            // the codes of both steps are loaded before any is decoded, from
+            // addresses clamped into the item (rank -> j0, row -> 0), then
+            // decoded, masked and rounded to W
             V8 a[2][PG], b[2][NT];
+            RawCodes<F, kKL> rv[2][PG];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int row = (st + h * kWaves) * kStep + g * kKL;   // nr and row are multiples of 8
@@ -103,12 +97,23 @@ __device__ void contract_item_lp(const KParams& kp, const CItem& it, const Block
 #pragma unroll
                 for (int pg = 0; pg < PG; ++pg) {
                     const int j = j0 + 16 * pg + li;
-                    a[h][pg] = (ok && j < p) ? codes_to_w8<F, W>(Vp + (int64_t(j) * ld + row) * S) : zero;
+                    rv[h][pg].load(Vp + (int64_t(j < p ? j : j0) * ld + (ok ? row : 0)) * S);
                 }
 #pragma unroll
                 for (int ct = 0; ct < NT; ++ct) {
                     const int c = c0 + 16 * ct + li;
                     b[h][ct] = (ok && c < nrhs) ? load_w8<W>(X8 + (((prow0 + row) >> 3) * nrhs + c) * 8) : zero;
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const bool ok = (st + h * kWaves) * kStep + g * kKL < it.nr;
+#pragma unroll
+                for (int pg = 0; pg < PG; ++pg) {
+                    CodeT<F> v[kKL];
+                    rv[h][pg].template decode<CodeT<F>>(v, ok && j0 + 16 * pg + li < p);
+#pragma unroll
+                    for (int q = 0; q < kKL; ++q) a[h][pg][q] = W(v[q]);
                 }
             }
 #pragma unroll
