@@ -40,7 +40,12 @@ traffic: HBM bytes per launch of that kernel from rocprofv3 counters
 The default run also measures, as keys of the same line, the 262144-point
 fp8 operator with 128 right-hand sides (fp32 and bf16 working precision),
 the 2^20-point fp64-accumulated operator with 16 right-hand sides and the
-512-operator batch, each with its own timing, roofline and oracle check.
+512-operator batch, each with its own timing, roofline and oracle check;
+and, on the headline operator, its construction on the GPU from the kernel
+(hodlr_build_kernel: time, and norms, formats and ranks against the host
+compressor's) and its LU (factorization time on the host, GPU solve time,
+and the solve's residual against Cor. "LU of mixed-precision HODLR
+matrices").
 speedup_vs_fp64: the same operators with every level stored in fp64 and
 fp64 accumulation (the uniform-precision product on the same GPU).
 storage_ratio: uniform-fp64 bits over the stored bits (Sect. 4 storage
@@ -141,7 +146,8 @@ def build_operator(cfg, H):
     t = time.time()
     op = compress(cfg.kernel, P, blocks, leaves, cfg.eps, cfg.rule, norm_a_2(cfg, P),
                   method=cfg.extra.get("compress", "random"))
-    log(f"[bench] compressed {cfg.name}: n={cfg.n} depth={cfg.depth} in {time.time() - t:.1f}s")
+    op.host_seconds = time.time() - t
+    log(f"[bench] compressed {cfg.name}: n={cfg.n} depth={cfg.depth} in {op.host_seconds:.1f}s")
     return op
 
 
@@ -495,6 +501,71 @@ def single_workload(name, nrhs_list, args, flush, torch, H, with_cpu, headline):
 
 
 # ---------------------------------------------------------------------------
+# construction on the GPU and the LU solve, on the headline workload
+# ---------------------------------------------------------------------------
+# the library's description of each recipe's kernel matrix (hodlr_build_kernel)
+LIB_KERNELS = {"c2": dict(kind="gaussian", a=0.04, diag_shift=0.01)}
+
+
+def construct_lu_workload(state, torch, H, solves=10):
+    """The headline operator built on the GPU from its kernel (compared with
+    the host compressor's exact norms, formats and ranks), its LU on the
+    host, and the GPU solve with the inverse factors (residual against
+    Cor. "LU of mixed-precision HODLR matrices")."""
+    cfg, op, h, fmts, norms2 = state
+    if cfg.name not in LIB_KERNELS:
+        return None
+    P = cfg.points()
+    torch.cuda.synchronize()
+    t = time.time()
+    hb, rep = H.build_kernel(P, cfg.depth, eps=cfg.eps, seed=7, **LIB_KERNELS[cfg.name])
+    torch.cuda.synchronize()
+    wall = time.time() - t
+    got = hb.norms2()
+    norm_rel = float(np.max(np.abs(got - norms2) / np.maximum(np.abs(norms2), 1e-300)))
+    hb.assign_precision(cfg.eps, cfg.allowed)               # from the norms the construction kept
+    gfmts = [lv[0] for lv in hb.levels()]
+    dr = np.array(hb.query()["ranks"]) - np.array(op.ranks)
+    log(f"[bench] {cfg.name} built on the GPU in {wall:.2f}s (host compressor "
+        f"{getattr(op, 'host_seconds', float('nan')):.1f}s); norms rel diff {norm_rel:.1e}, "
+        f"formats {gfmts}, rank diff [{dr.min()}, {dr.max()}]")
+    out = {"construct": {"seconds": round(wall, 3), "report_ms": {k: round(rep[k], 1) for k in
+                                                                   ("ms_norms", "ms_factors", "ms_total")},
+                         "host_compressor_seconds": round(getattr(op, "host_seconds", float("nan")), 2),
+                         "max_rank": rep["max_rank"],
+                         "check": {"norms_max_rel_diff": norm_rel, "formats_equal": gfmts == fmts,
+                                   "rank_diff_min": int(dr.min()), "rank_diff_max": int(dr.max())}}}
+    t = time.time()
+    lrep = hb.lu(cfg.eps)
+    lu_wall = time.time() - t
+    b = np.random.default_rng(21).standard_normal((cfg.n, 1))
+    B = H.colmajor_empty(cfg.n, 1, torch.float64, "cuda:0")
+    B.copy_(torch.from_numpy(np.asfortranarray(b)))
+    X = H.colmajor_empty(cfg.n, 1, torch.float64, "cuda:0")
+    hb.solve(B, X)                                          # workspaces
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(solves):
+        hb.solve(B, X)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / solves
+    res = float(torch.linalg.vector_norm(hb.matvec(X) - B)) / float(torch.linalg.vector_norm(X))
+    # Cor. "LU of mixed-precision HODLR matrices": 2 (2^l - 1) eps ||H|| + 11 (2^l - 1) eps ||L|| ||U||
+    c = 2 ** cfg.depth - 1
+    bound = 2 * c * cfg.eps * float(np.sqrt(norms2[0])) + 11 * c * cfg.eps * lrep["norm_l"] * lrep["norm_u"]
+    log(f"[bench] {cfg.name} LU on the host {lu_wall:.1f}s; GPU solve {ms:.3f} ms; ||Hx-b||/||x|| {res:.2e} "
+        f"(bound {bound:.2e})")
+    out["lu"] = {"factor_seconds": round(lu_wall, 2), "solve_ms": round(ms, 4), "nrhs": 1,
+                 "max_rank": lrep["max_rank"], "norm_l": lrep["norm_l"], "norm_u": lrep["norm_u"],
+                 "check": {"residual_over_norm_x": res, "corollary_bound": bound, "within": res <= bound}}
+    hb.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
 # the product in a low working precision
 # ---------------------------------------------------------------------------
 def lowp_workload(state, w, nrhs, args, flush, torch, H):
@@ -813,9 +884,12 @@ def main():
     out.update(head)
     out["dtype"] = "f32+f64" if cfg.x_dtype == "fp32" else "f64"
     if not args.only:
+        extra = {}
+        cl = construct_lu_workload(state, torch, H)
+        if cl is not None:
+            extra[f"{cfg.name}_construct_lu"] = cl
         state[2].close()
         del state
-        extra = {}
         # the low-accuracy fp8 operator with 128 right-hand sides: fp32 X (fp64 MFMA leaves), then bf16 X
         r3, st3 = single_workload("c3", [128], args, flush, torch, H, False, False)
         extra["c3"] = r3
