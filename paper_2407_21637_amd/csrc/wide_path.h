@@ -323,12 +323,17 @@ __device__ void expand_level_w(const KParams& kp, const BlockDesc& bd, int chunk
                 // panel (rank -> the chunk's first staged rank, inactive
                 // rows -> row 0), and masked when decoded
                 RawCodes<F, 1> u0[QG], u1[QG];
-#pragma unroll
-                for (int q = 0; q < QG; ++q) {
+                auto issue = [&](int q) {
                     const int jr = j0 + 4 * q + g;
                     const uint8_t* col = Up + int64_t(cr0 + (jr < crows ? jr : 0)) * ld * S;
                     u0[q].load(col + int64_t(act0 ? r0 : 0) * S);
                     u1[q].load(col + int64_t(act1 ? r1 : 0) * S);
+                };
+#pragma unroll
+                for (int q = 0; q < QG / 2; ++q) issue(q);
+                if (__builtin_amdgcn_readfirstlane(qn) > QG / 2) {   // the second half only when used
+#pragma unroll
+                    for (int q = QG / 2; q < QG; ++q) issue(q);
                 }
 #pragma unroll
                 for (int q = 0; q < QG; ++q) {
