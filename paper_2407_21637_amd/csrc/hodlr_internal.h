@@ -73,6 +73,47 @@ struct BlockDesc {        // one per off-diagonal block, canonical order
     int32_t pad_;         // rows of a contraction item (V panel chunk)
     int64_t tw_off;       // low working precision: offset of T_b in W, in units of
                           // round_up(rank, 32) (x nrhs values, [c][j])
+    int64_t s_off;        // matrix-core contraction: per-leaf partials of T_b, offset in units
+                          // of rank (x nrhs doubles), one rank x nrhs slice per leaf of the
+                          // column node
+    int32_t sleaf0;       // first leaf of the column node
+    int32_t sleaves;      // leaves of the column node
+};
+
+// Reduction of the per-leaf partials of a block with `leaves` leaves in its
+// column node: the 256 threads of a workgroup take 256 / slices outputs and
+// split the leaves into `slices` interleaved runs (at most 8 leaves a run
+// up to 512 leaves), then add the runs in order.
+constexpr int stack_slices(int leaves) {
+    int s = 1;
+    while (s * 8 < leaves && s < 64) s *= 2;
+    return s;
+}
+
+// Matrix-core contraction (nrhs >= kWideMin): each leaf's work is cut into
+// tiles of up to 16 MFMA rows, each row one rank j of one ancestor block
+// whose V panel covers the leaf's rows (the block of level k whose column
+// node holds the leaf).  A tile's rows share the code format and the
+// arithmetic type (fp64 for fp64 codes or fp64 accumulation, else the
+// accumulation type), so X is read once per leaf for all levels.
+constexpr int kStackRows = 16;
+struct STile {
+    int32_t fmt;               // code format of every row
+    int32_t dbl;               // 1: multiplied in fp64, 0: in the accumulation type
+    int32_t n;                 // rows in use; rows n..15 repeat row 0 and are masked
+    int32_t pad_;
+    int32_t blk[kStackRows];   // block of each row
+    int32_t j[kStackRows];     // rank of each row within its block
+};
+
+// A workgroup's share of the matrix-core contraction: ng consecutive tiles
+// of one leaf with one format and arithmetic type (up to 2 in fp64, 4 in
+// fp32), one pass over the leaf's rows.
+struct SUnit {
+    int32_t leaf;
+    int32_t t0;                // first tile (index into the tiles)
+    int32_t ng;
+    int32_t pad_;
 };
 
 struct LeafDesc {
@@ -109,6 +150,9 @@ struct KParams {
     const BlockDesc* blocks;
     const LeafDesc* leaves;
     const CItem* citems;
+    const STile* stiles;         // matrix-core contraction tiles, leaf by leaf
+    const int32_t* stile_off;    // first tile of each leaf (nleaves + 1 values)
+    const SUnit* sunits;         // matrix-core contraction units (nsunits)
     const ETile* etiles;
     const double* tscale;
     const void* aug;             // low working precision: the augmented operands in W (LeafDesc::aug_off)
@@ -126,6 +170,8 @@ struct KParams {
     int32_t nblocks;
     int32_t nleaves;
     int32_t ncitems;
+    int32_t nsunits;
+    int32_t stacked;             // matrix-core contraction by stacked tiles (SUnit) instead of items
     int32_t netiles;
     int32_t padded;              // 1 if any leaf has padding rows (X goes through xpad)
     int32_t max_block_rank;      // largest rank of a block
@@ -133,6 +179,7 @@ struct KParams {
                                  // blocks, of round_up(rank, 4) * (8 if fp64 else 4) bytes
                                  // (T of every level staged in LDS, per LDS row element)
     int32_t max_kp;              // low working precision: largest LeafDesc::kp
+    int32_t level_max_rank[kMaxDepth];   // largest rank of a block of level k (index k - 1)
 };
 
 // Counters of the contraction launch: kSyncHead reserved words, then one
@@ -217,6 +264,8 @@ struct WorkItem {              // (operator, leaf / item / block / tile, right-h
 struct BatchGroup {
     int32_t xy_double, acc_double, wide, rg, ntc;
     int32_t stage_cap, jc;
+    int32_t stacked;           // matrix cores: contraction by stacked tiles (every operator of the group)
+    int32_t pad_;
     int64_t lds_contract, lds_expand;
     const BatchOp* ops;        // device
     const WorkItem* padx;      // device arrays and their lengths

@@ -279,6 +279,11 @@ struct hodlr_op_s {
     int64_t total_rank = 0;    // sum of ranks (T slots)
     int64_t total_rank32 = 0;  // sum of ranks rounded up to 32 (T slots in a low working precision)
     int64_t total_item_rank = 0;
+    std::vector<STile> stiles;                 // matrix-core contraction tiles (see stack_tiles)
+    std::vector<int32_t> stile_off;            // per leaf, nleaves + 1
+    std::vector<SUnit> sunits;                 // contraction units (groups of tiles)
+    int64_t total_stack_rank = 0;              // sum over blocks of rank x leaves of the column node
+    bool stacked = false;                      // see stack_tiles
     int64_t codes_bytes = 0;   // sum (r+c) p s(f)
     int64_t scaled_cols = 0;
     int32_t max_leaf = 0;
@@ -298,6 +303,9 @@ struct hodlr_op_s {
     BlockDesc* d_blocks = nullptr;
     LeafDesc* d_leaves = nullptr;
     CItem* d_citems = nullptr;
+    STile* d_stiles = nullptr;
+    int32_t* d_stile_off = nullptr;
+    SUnit* d_sunits = nullptr;
     ETile* d_etiles = nullptr;
     double* d_tscale = nullptr;
     std::mutex ws_mu;
@@ -356,6 +364,9 @@ void free_device(hodlr_op_s* op) {
     dev_free(op->d_blocks);
     dev_free(op->d_leaves);
     dev_free(op->d_citems);
+    dev_free(op->d_stiles);
+    dev_free(op->d_stile_off);
+    dev_free(op->d_sunits);
     dev_free(op->d_etiles);
     dev_free(op->d_tscale);
     op->d_fac = nullptr;
@@ -363,6 +374,9 @@ void free_device(hodlr_op_s* op) {
     op->d_blocks = nullptr;
     op->d_leaves = nullptr;
     op->d_citems = nullptr;
+    op->d_stiles = nullptr;
+    op->d_stile_off = nullptr;
+    op->d_sunits = nullptr;
     op->d_etiles = nullptr;
     op->d_tscale = nullptr;
     for (auto& kv : op->ws) {
@@ -488,6 +502,76 @@ void node_rowlocs(const hodlr_op_s* op, int k, int64_t j, int64_t chunk_rows, st
     }
 }
 
+// Tiles of the matrix-core contraction (STile): for every leaf, the ranks
+// of the depth blocks whose V panels cover its rows (level k: the block
+// whose column node holds the leaf), grouped by arithmetic type and code
+// format, 16 to a tile; and, per block, where its per-leaf partials go.
+// Which other rows share a row's tile does not change that row's sums.
+void stack_tiles(hodlr_op_s* op) {
+    const int depth = op->depth, nl = op->nleaves;
+    int64_t soff = 0;
+    for (int b = 0; b < op->nb; ++b) {
+        BlockDesc& d = op->bdesc[size_t(b)];
+        const int k = d.level;
+        const int64_t jrow = b - ((int64_t(1) << k) - 2);
+        d.sleaves = int32_t(int64_t(1) << (depth - k));
+        d.sleaf0 = int32_t((jrow ^ 1) << (depth - k));
+        d.s_off = soff;
+        soff += int64_t(d.rank) * d.sleaves;
+    }
+    op->total_stack_rank = soff;
+    op->stiles.clear();
+    op->stile_off.assign(size_t(nl) + 1, 0);
+    for (int i = 0; i < nl; ++i) {
+        op->stile_off[size_t(i)] = int32_t(op->stiles.size());
+        // (arithmetic type, format) -> its rows, levels in order
+        std::map<std::pair<int, int>, std::vector<std::pair<int32_t, int32_t>>> groups;
+        for (int k = 1; k <= depth; ++k) {
+            const int b = ((1 << k) - 2) + ((i >> (depth - k)) ^ 1);
+            const BlockDesc& d = op->bdesc[size_t(b)];
+            const int dbl = (op->acc_double || d.fmt == F64) ? 1 : 0;
+            auto& rows = groups[{-dbl, d.fmt}];              // fp64 tiles first
+            for (int j = 0; j < d.rank; ++j) rows.push_back({b, j});
+        }
+        for (const auto& g : groups) {
+            const auto& rows = g.second;
+            for (size_t r0 = 0; r0 < rows.size(); r0 += kStackRows) {
+                STile t{};
+                t.fmt = g.first.second;
+                t.dbl = -g.first.first;
+                t.n = int32_t(std::min<size_t>(kStackRows, rows.size() - r0));
+                for (int q = 0; q < kStackRows; ++q) {
+                    const auto& rw = rows[r0 + (q < t.n ? size_t(q) : 0)];
+                    t.blk[q] = rw.first;
+                    t.j[q] = rw.second;
+                }
+                op->stiles.push_back(t);
+            }
+        }
+    }
+    op->stile_off[size_t(nl)] = int32_t(op->stiles.size());
+    // units: consecutive tiles of a leaf with one format and arithmetic type, up to 2 (fp64) or 4
+    op->sunits.clear();
+    for (int i = 0; i < nl; ++i) {
+        const int t1 = op->stile_off[size_t(i) + 1];
+        for (int t = op->stile_off[size_t(i)]; t < t1;) {
+            const STile& a = op->stiles[size_t(t)];
+            const int cap = a.dbl ? 2 : 4;
+            int ng = 1;
+            while (ng < cap && t + ng < t1 && op->stiles[size_t(t + ng)].fmt == a.fmt &&
+                   op->stiles[size_t(t + ng)].dbl == a.dbl)
+                ++ng;
+            op->sunits.push_back(SUnit{i, t, ng, 0});
+            t += ng;
+        }
+    }
+    // The stacked contraction reads X once per leaf only when each leaf is
+    // one unit (one pass); with more passes the per-level items, whose long
+    // runs of rows keep more loads in flight, are faster (measured on the
+    // 512-operator batch), so they are used instead.
+    op->stacked = !op->sunits.empty() && op->sunits.size() == size_t(nl);
+}
+
 // Build descriptors, quantise every factor into a host staging image and
 // (for device handles) upload it.  Called after create and after every
 // precision change.
@@ -547,6 +631,7 @@ hodlr_status pack(hodlr_op_s* op) {
         op->codes_bytes += (hb.nrows + hb.ncols) * p * fmt_bytes(f);
         if (op->scale_cols && scaled_format(f)) op->scaled_cols += 2 * p;
     }
+    stack_tiles(op);
     op->fac_bytes = std::max<int64_t>(off, kPanelAlign);
     op->total_rank = toff;
     op->total_rank32 = twoff;
@@ -627,6 +712,12 @@ hodlr_status pack(hodlr_op_s* op) {
     if ((r = upload(&op->d_blocks, op->bdesc.data(), op->bdesc.size(), "block table")) != HODLR_OK)
         return r;
     if ((r = upload(&op->d_citems, op->citems.data(), op->citems.size(), "work items")) != HODLR_OK)
+        return r;
+    if ((r = upload(&op->d_stiles, op->stiles.data(), op->stiles.size(), "contraction tiles")) != HODLR_OK)
+        return r;
+    if ((r = upload(&op->d_stile_off, op->stile_off.data(), op->stile_off.size(), "contraction tiles")) != HODLR_OK)
+        return r;
+    if ((r = upload(&op->d_sunits, op->sunits.data(), op->sunits.size(), "contraction units")) != HODLR_OK)
         return r;
     if ((r = upload(&op->d_tscale, tscale.data(), tscale.size(), "column scales")) != HODLR_OK)
         return r;
@@ -1182,7 +1273,10 @@ WsNeeds workspace_needs(const hodlr_op_s* op, int nrhs, int xy_bytes) {
     // which reads X with 16-byte vector loads and copies it when it is not aligned
     // (the low working precision path, 2-byte X, always runs on the matrix cores)
     const bool lowp = xy_bytes == 2;
-    n.partial = std::max<int64_t>(1, op->total_item_rank * nrhs) * 8;
+    // partials: per contraction item below kWideMin columns, per (block, leaf) at or above
+    n.partial = std::max<int64_t>(1, (nrhs >= kWideMin && !lowp && op->stacked ? op->total_stack_rank
+                                                                                : op->total_item_rank) *
+                                         nrhs) * 8;
     n.T = std::max<int64_t>(1, op->total_rank * nrhs) * 8;
     n.xpad = (op->padded || nrhs >= kWideMin || lowp) ? op->npad * nrhs * xy_bytes : 0;
     n.W = (nrhs < kWideMin && !lowp) ? op->npad * nrhs * 8 : 0;
@@ -1198,6 +1292,16 @@ void fill_kparams(const hodlr_op_s* op, KParams* kp) {
     kp->blocks = op->d_blocks;
     kp->leaves = op->d_leaves;
     kp->citems = op->d_citems;
+    kp->stiles = op->d_stiles;
+    kp->stile_off = op->d_stile_off;
+    kp->sunits = op->d_sunits;
+    kp->nsunits = int32_t(op->sunits.size());
+    kp->stacked = op->stacked ? 1 : 0;
+    for (int k = 0; k < kMaxDepth; ++k) kp->level_max_rank[k] = 0;
+    for (int b = 0; b < op->nb; ++b) {
+        const int k = op->bdesc[size_t(b)].level;
+        kp->level_max_rank[k - 1] = std::max(kp->level_max_rank[k - 1], op->rank[size_t(b)]);
+    }
     kp->etiles = op->d_etiles;
     kp->tscale = op->d_tscale;
     kp->npad = op->npad;
@@ -1363,7 +1467,8 @@ hodlr_status build_plan(const hodlr_op* ops, int count, const void* const* X, co
         if (plan_launch(kp, X[i], ldx[i], nrhs[i], xyd, op->acc_double, &ol) != 0)
             return fail(HODLR_E_UNSUPPORTED, "operator %d: leaf size %d with path rank %d needs more than 64 KB of LDS",
                         i, op->max_leaf, op->max_rank_path);
-        const std::vector<int32_t> key = {xyd ? 1 : 0, op->acc_double ? 1 : 0, ol.wide, ol.rg};
+        const std::vector<int32_t> key = {xyd ? 1 : 0, op->acc_double ? 1 : 0, ol.wide, ol.rg,
+                                          (ol.wide && op->stacked) ? 1 : 0};
         GroupBuild& gb = groups[key];
         BatchGroup& g = gb.g;
         if (gb.ops.empty()) {
@@ -1373,6 +1478,7 @@ hodlr_status build_plan(const hodlr_op* ops, int count, const void* const* X, co
             g.rg = ol.rg;
             g.ntc = ol.ntc;
             g.jc = 0;
+            g.stacked = key[4];
         }
         g.stage_cap = std::max(g.stage_cap, ol.stage_cap);
         g.lds_contract = std::max(g.lds_contract, ol.lds_contract);
@@ -1394,11 +1500,22 @@ hodlr_status build_plan(const hodlr_op* ops, int count, const void* const* X, co
             for (int l = 0; l < op->nleaves; ++l)
                 gb.work[0].push_back({int64_t(op->ldesc[l].mp) * s_rhs, WorkItem{oi, l, 0, 0}});
         const int gyc = ol.wide ? ol.gy_contract : 1;
-        for (int c = 0; c < int(op->citems.size()); ++c) {
-            const CItem& it = op->citems[c];
-            const BlockDesc& bd = op->bdesc[it.block];
-            const int64_t cost = int64_t(it.nr) * bd.rank * fmt_bytes(bd.fmt) + int64_t(it.nr) * 4 * s_rhs;
-            for (int y = 0; y < gyc; ++y) gb.work[1].push_back({cost, WorkItem{oi, c, y, 0}});
+        if (ol.wide && op->stacked) {   // matrix cores, stacked: one work item per (unit, column group)
+            for (int u = 0; u < int(op->sunits.size()); ++u) {
+                const SUnit& su = op->sunits[size_t(u)];
+                const int64_t mp = op->ldesc[size_t(su.leaf)].mp;
+                int64_t cost = mp * 4 * s_rhs;
+                for (int t = su.t0; t < su.t0 + su.ng; ++t)
+                    cost += mp * op->stiles[size_t(t)].n * fmt_bytes(op->stiles[size_t(t)].fmt);
+                for (int y = 0; y < gyc; ++y) gb.work[1].push_back({cost, WorkItem{oi, u, y, 0}});
+            }
+        } else {
+            for (int c = 0; c < int(op->citems.size()); ++c) {
+                const CItem& it = op->citems[c];
+                const BlockDesc& bd = op->bdesc[it.block];
+                const int64_t cost = int64_t(it.nr) * bd.rank * fmt_bytes(bd.fmt) + int64_t(it.nr) * 4 * s_rhs;
+                for (int y = 0; y < gyc; ++y) gb.work[1].push_back({cost, WorkItem{oi, c, y, 0}});
+            }
         }
         if (!ol.wide)             // the wave path's first launch also runs the leaf tiles (y = 1)
             for (int t = 0; t < int(op->etiles.size()); ++t) {
@@ -1407,9 +1524,12 @@ hodlr_status build_plan(const hodlr_op* ops, int count, const void* const* X, co
             }
         if (ol.wide && !op->citems.empty())
             for (int b = 0; b < op->nb; ++b) {
-                const int64_t total = int64_t(op->bdesc[b].rank) * nrhs[i];
-                for (int64_t y = 0; y * 256 < total; ++y)
-                    gb.work[2].push_back({int64_t(op->bdesc[b].nitems), WorkItem{oi, b, int32_t(y), 0}});
+                const BlockDesc& bd = op->bdesc[b];
+                const int64_t total = int64_t(bd.rank) * nrhs[i];
+                const int out = op->stacked ? 256 / stack_slices(bd.sleaves) : 256;
+                for (int64_t y = 0; y * out < total; ++y)
+                    gb.work[2].push_back({op->stacked ? int64_t(bd.sleaves) : int64_t(bd.nitems),
+                                          WorkItem{oi, b, int32_t(y), 0}});
             }
         const int gye = ol.wide ? ol.gy_expand : 1;
         for (int t = 0; t < int(op->etiles.size()); ++t) {
@@ -1494,8 +1614,9 @@ hodlr_status build_plan(const hodlr_op* ops, int count, const void* const* X, co
             int64_t cost = 0;
             for (auto& w : kv.second.work[ph]) cost += w.first;
             char buf[160];
-            std::snprintf(buf, sizeof(buf), "x%d.a%d.w%d.r%d.ph%d.n%d.c%d", kv.first[0], kv.first[1], kv.first[2],
-                          kv.first[3], ph, lg(int64_t(kv.second.work[ph].size())), lg(cost));
+            std::snprintf(buf, sizeof(buf), "x%d.a%d.w%d.r%d.s%d.ph%d.n%d.c%d", kv.first[0], kv.first[1],
+                          kv.first[2], kv.first[3], kv.first[4], ph, lg(int64_t(kv.second.work[ph].size())),
+                          lg(cost));
             cls[ph] = buf;
         }
         plan->shape.push_back(cls);

@@ -65,25 +65,25 @@ __global__ __launch_bounds__(kExpandThreads) void kb_expand(const BatchOp* __res
     }
 }
 
-template <typename XT, typename AT, int NT>
+template <typename XT, typename AT, int NT, bool STACK>
 __global__ __launch_bounds__(kThreads) void kb_contract_w(const BatchOp* __restrict__ ops,
                                                           const WorkItem* __restrict__ w, int nw) {
     extern __shared__ double smem_d[];
     for (int i = blockIdx.x; i < nw; i += gridDim.x) {
         const WorkItem wi = w[i];
         const BatchOp o = ops[wi.op];                  // uniform: the step's operator
-        run_contract_w<XT, AT, NT>(o.kp, wi.idx, wi.y, static_cast<const XT*>(o.Xc), o.ldc, o.nrhs, smem_d);
+        run_contract_w<XT, AT, NT, STACK>(o.kp, wi.idx, wi.y, static_cast<const XT*>(o.Xc), o.ldc, o.nrhs, smem_d);
         __syncthreads();
     }
 }
 
-template <typename AT>
+template <typename AT, bool STACK>
 __global__ __launch_bounds__(256) void kb_reduce_w(const BatchOp* __restrict__ ops, const WorkItem* __restrict__ w,
                                                    int nw) {
     for (int i = blockIdx.x; i < nw; i += gridDim.x) {
         const WorkItem wi = w[i];
         const BatchOp o = ops[wi.op];                  // uniform: the step's operator
-        run_reduce_w<AT>(o.kp, wi.idx, wi.y, o.nrhs);
+        run_reduce_w<AT, STACK>(o.kp, wi.idx, wi.y, o.nrhs);
     }
 }
 
@@ -120,11 +120,20 @@ hipError_t batch_wide(const BatchGroup& g, hipStream_t s) {
     constexpr int NTC = NT > 4 ? 4 : NT;                // as the single-operator launch
     if (g.n_padx)
         hipLaunchKernelGGL((kb_padx<XT>), dim3(g.grid[0]), dim3(256), 0, s, g.ops, g.padx, g.n_padx);
-    if (g.n_contract)
-        hipLaunchKernelGGL((kb_contract_w<XT, AT, NTC>), dim3(g.grid[1]), dim3(kThreads), size_t(g.lds_contract), s,
-                           g.ops, g.contract, g.n_contract);
-    if (g.n_reduce)
-        hipLaunchKernelGGL((kb_reduce_w<AT>), dim3(g.grid[2]), dim3(256), 0, s, g.ops, g.reduce, g.n_reduce);
+    if (g.n_contract) {
+        if (g.stacked)
+            hipLaunchKernelGGL((kb_contract_w<XT, AT, NTC, true>), dim3(g.grid[1]), dim3(kThreads),
+                               size_t(g.lds_contract), s, g.ops, g.contract, g.n_contract);
+        else
+            hipLaunchKernelGGL((kb_contract_w<XT, AT, NTC, false>), dim3(g.grid[1]), dim3(kThreads),
+                               size_t(g.lds_contract), s, g.ops, g.contract, g.n_contract);
+    }
+    if (g.n_reduce) {
+        if (g.stacked)
+            hipLaunchKernelGGL((kb_reduce_w<AT, true>), dim3(g.grid[2]), dim3(256), 0, s, g.ops, g.reduce, g.n_reduce);
+        else
+            hipLaunchKernelGGL((kb_reduce_w<AT, false>), dim3(g.grid[2]), dim3(256), 0, s, g.ops, g.reduce, g.n_reduce);
+    }
     if (g.n_expand)
         hipLaunchKernelGGL((kb_expand_w<XT, AT, NT>), dim3(g.grid[3]), dim3(kThreads), size_t(g.lds_expand), s,
                            g.ops, g.expand, g.n_expand, int(g.lds_expand), g.jc);

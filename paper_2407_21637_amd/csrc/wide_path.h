@@ -91,7 +91,153 @@ __device__ __forceinline__ void load_x8(const XT* p, CT v[kKL]) {
     }
 }
 
-// Contraction item on the matrix cores: partial T_b over rows [r0, r0+nr)
+// Contraction on the matrix cores, one leaf at a time: the partial T_b of
+// every ancestor block over the leaf's rows (the block of level k whose V
+// panel covers them), for right-hand sides [c0, c0 + 16 NT).  The leaf's
+// (block, rank) rows are stacked 16 to an MFMA tile (STile); a group of TG
+// tiles of one format and arithmetic type is one pass over the leaf's rows
+// (X comes from HBM for the first group, from the caches for the others).
+// The waves split the rows in 32-row steps; lane group g of a step holds
+// rows 8g..8g+7; every tile's codes are loaded before any is decoded; the
+// four waves' blocks are added in LDS (`red`) and stored as the leaf's
+// slice of each block's partials ([j][c], ld nrhs).
+template <int F, typename CT, typename XT, int NT, int TG>
+__device__ void contract_group_s(const KParams& kp, const LeafDesc& L, int leaf, const STile* __restrict__ tiles,
+                                 int ng, const XT* __restrict__ X, int64_t ldx, int nrhs, int c0, CT* red) {
+    using M = Mfma<CT>;
+    constexpr int S = Codec<F>::kBytes;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    // the lane's row of each tile: its block's V panel (chunked every pad_
+    // rows, see the packer) and the leaf's first row in it; rows past a
+    // tile's n repeat its row 0 (valid addresses) and are masked
+    const uint8_t* vb[TG];
+    int vr0[TG], vch[TG], vrows[TG], vp[TG], vj[TG];
+    bool vok[TG];
+#pragma unroll
+    for (int tg = 0; tg < TG; ++tg) {
+        const int t = tg < ng ? tg : 0;
+        const BlockDesc& bd = kp.blocks[tiles[t].blk[li]];
+        vok[tg] = tg < ng && li < tiles[t].n;
+        vb[tg] = kp.fac + bd.v_off;
+        vr0[tg] = L.prow0 - bd.vrow0;
+        vch[tg] = bd.pad_;
+        vrows[tg] = bd.vrows;
+        vp[tg] = bd.rank;
+        vj[tg] = tiles[t].j[li];
+    }
+    typename M::acc_t acc[TG][NT];
+#pragma unroll
+    for (int a = 0; a < TG; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) zero_acc(acc[a][b]);
+    const XT* Xr = X + L.prow0;
+    const int nstep = (L.mp + kStep - 1) / kStep;
+    for (int st = wave; st < nstep; st += kWaves) {
+        const int row = st * kStep + g * kKL;           // mp and row are multiples of 8
+        const bool ok = row < L.mp;
+        const int rowc = ok ? row : 0;
+        RawCodes<F, kKL> rv[TG];
+#pragma unroll
+        for (int tg = 0; tg < TG; ++tg) {
+            const int r = vr0[tg] + rowc;               // row in the panel
+            const int cs = (r / vch[tg]) * vch[tg];     // its chunk: first row and rows
+            const int rows_c = min(vch[tg], vrows[tg] - cs);
+            rv[tg].load(vb[tg] + (int64_t(cs) * vp[tg] + int64_t(vj[tg]) * rows_c + (r - cs)) * S);
+        }
+        CT a[TG][kKL], b[NT][kKL];
+        if constexpr (sizeof(XT) == sizeof(CT)) {
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+                const int c = c0 + 16 * ct + li;
+                if (ok && c < nrhs)
+                    load_x8<XT, CT>(Xr + row + ldx * c, b[ct]);
+                else
+#pragma unroll
+                    for (int q = 0; q < kKL; ++q) b[ct][q] = CT(0);
+            }
+        } else {
+            // X converted to CT: loaded first (column -> c0, row -> 0), converted after
+            RawX<XT, kKL> rx[NT];
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+                const int c = c0 + 16 * ct + li;
+                rx[ct].load(Xr + rowc + ldx * (c < nrhs ? c : c0));
+            }
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) rx[ct].template convert<CT>(b[ct], ok && c0 + 16 * ct + li < nrhs);
+        }
+#pragma unroll
+        for (int tg = 0; tg < TG; ++tg) rv[tg].template decode<CT>(a[tg], ok && vok[tg]);
+#pragma unroll
+        for (int q = 0; q < kKL; ++q)
+#pragma unroll
+            for (int tg = 0; tg < TG; ++tg)
+                if (tg < ng)
+#pragma unroll
+                    for (int ct = 0; ct < NT; ++ct) acc[tg][ct] = M::mma(a[tg][q], b[ct][q], acc[tg][ct]);
+    }
+    // add the four waves' blocks, one tile at a time, and store each row's slice
+#pragma unroll
+    for (int tg = 0; tg < TG; ++tg) {
+        if (tg >= ng) break;
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) red[(wave * NT + ct) * 256 + acc_row<CT>(g, e) * 16 + li] = acc[tg][ct][e];
+        __syncthreads();
+        const int n = tiles[tg].n;
+        for (int idx = threadIdx.x; idx < NT * 256; idx += kThreads) {
+            const int ct = idx >> 8, jr = (idx >> 4) & 15, cl = idx & 15;
+            const int c = c0 + 16 * ct + cl;
+            CT s = CT(0);
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) s += red[(w * NT) * 256 + idx];
+            if (jr < n && c < nrhs) {
+                const BlockDesc& bd = kp.blocks[tiles[tg].blk[jr]];
+                double* part = kp.partial + (bd.s_off + int64_t(leaf - bd.sleaf0) * bd.rank) * nrhs;
+                part[int64_t(tiles[tg].j[jr]) * nrhs + c] = double(s);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename CT, typename XT, int NT, int TG>
+__device__ void contract_group_dispatch(int fmt, const KParams& kp, const LeafDesc& L, int leaf,
+                                        const STile* tiles, int ng, const XT* X, int64_t ldx, int nrhs, int c0,
+                                        CT* red) {
+    switch (fmt) {
+        case F64: contract_group_s<F64, CT, XT, NT, TG>(kp, L, leaf, tiles, ng, X, ldx, nrhs, c0, red); break;
+        case F32: contract_group_s<F32, CT, XT, NT, TG>(kp, L, leaf, tiles, ng, X, ldx, nrhs, c0, red); break;
+        case BF16: contract_group_s<BF16, CT, XT, NT, TG>(kp, L, leaf, tiles, ng, X, ldx, nrhs, c0, red); break;
+        case F16: contract_group_s<F16, CT, XT, NT, TG>(kp, L, leaf, tiles, ng, X, ldx, nrhs, c0, red); break;
+        case E4M3: contract_group_s<E4M3, CT, XT, NT, TG>(kp, L, leaf, tiles, ng, X, ldx, nrhs, c0, red); break;
+        default: contract_group_s<E5M2, CT, XT, NT, TG>(kp, L, leaf, tiles, ng, X, ldx, nrhs, c0, red); break;
+    }
+}
+
+// One contraction unit (a group of tiles of one leaf) for right-hand-side group yg.
+template <typename XT, typename AT, int NT>
+__device__ void run_contract_stack(const KParams& kp, int unit, int yg, const XT* __restrict__ Xc, int64_t ldc,
+                               int nrhs, double* smem_d) {
+    const SUnit su = kp.sunits[unit];
+    const LeafDesc L = kp.leaves[su.leaf];
+    const STile* tiles = kp.stiles + su.t0;
+    const int fmt = tiles[0].fmt, dbl = tiles[0].dbl;
+    const int c0 = yg * 16 * NT;
+    if (dbl || sizeof(AT) == 8) {
+        contract_group_dispatch<double, XT, NT, 2>(fmt, kp, L, su.leaf, tiles, su.ng, Xc, ldc, nrhs, c0,
+                                                   reinterpret_cast<double*>(smem_d));
+    } else if constexpr (sizeof(AT) == 4) {
+        contract_group_dispatch<float, XT, NT, 4>(fmt, kp, L, su.leaf, tiles, su.ng, Xc, ldc, nrhs, c0,
+                                                  reinterpret_cast<float*>(smem_d));
+    }
+}
+
+
+// Contraction by items (operators whose leaves need more than one pass of
+// stacked tiles): item on the matrix cores, partial T_b over rows [r0, r0+nr)
 // of the V panel for right-hand sides [c0, c0 + 16 NT).  The waves split
 // the rows in 32-row steps; each keeps a (16 PG) x (16 NT) block of partial
 // sums per pass over the rank and the four are added in LDS (`red`).  The
@@ -196,7 +342,7 @@ __device__ void contract_item_w(const KParams& kp, const CItem& it, const BlockD
 }
 
 template <typename XT, typename AT, int NT>
-__device__ void run_contract_w(const KParams& kp, int item, int yg, const XT* __restrict__ Xc, int64_t ldc,
+__device__ void run_contract_items(const KParams& kp, int item, int yg, const XT* __restrict__ Xc, int64_t ldc,
                                int nrhs, double* smem_d) {
     const CItem it = kp.citems[item];
     const BlockDesc bd = kp.blocks[it.block];
@@ -209,13 +355,6 @@ __device__ void run_contract_w(const KParams& kp, int item, int yg, const XT* __
         case E4M3: contract_item_w<E4M3, AT, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<AT*>(smem_d)); break;
         default: contract_item_w<E5M2, AT, XT, NT>(kp, it, bd, Xc, ldc, nrhs, c0, reinterpret_cast<AT*>(smem_d)); break;
     }
-}
-
-template <typename XT, typename AT, int NT>
-__global__ __launch_bounds__(kThreads) void k_contract_w(KParams kp, const XT* __restrict__ Xc, int64_t ldc,
-                                                         int nrhs) {
-    extern __shared__ double smem_d[];
-    run_contract_w<XT, AT, NT>(kp, blockIdx.x, blockIdx.y, Xc, ldc, nrhs, smem_d);
 }
 
 // T_b = tscale .* (sum of the block's item partials, in item order): one
@@ -239,7 +378,7 @@ __device__ void reduce_block(const KParams& kp, const BlockDesc& bd, int o, int 
 }
 
 template <typename AT>
-__device__ void run_reduce_w(const KParams& kp, int block, int yg, int nrhs) {
+__device__ void run_reduce_items(const KParams& kp, int block, int yg, int nrhs) {
     const BlockDesc bd = kp.blocks[block];
     const int total = bd.rank * nrhs;
     const int o = yg * 256 + threadIdx.x;
@@ -250,9 +389,112 @@ __device__ void run_reduce_w(const KParams& kp, int block, int yg, int nrhs) {
         reduce_block<AT>(kp, bd, o, total, nrhs);
 }
 
+// T_b = tscale .* (sum over the leaves of the column node of their partial
+// slices), outputs o = j * nrhs + c, 256 / SL per workgroup (chunk yg),
+// SL = stack_slices(leaves): thread (o, s) adds the slices s, s + SL, ...
+// in order (eight loads issued before their adds), then the SL runs are
+// added in order.  fp64 blocks add in fp64, others in the accumulation type.
 template <typename AT>
-__global__ __launch_bounds__(256) void k_reduce_w(KParams kp, int nrhs) {
-    run_reduce_w<AT>(kp, blockIdx.x, blockIdx.y, nrhs);
+__device__ void run_reduce_stack(const KParams& kp, int block, int yg, int nrhs) {
+    __shared__ double sred[256];
+    const BlockDesc bd = kp.blocks[block];
+    const int total = bd.rank * nrhs;
+    const int sl = stack_slices(bd.sleaves), out = 256 / sl;
+    if (yg * out >= total) return;                      // whole block: before the barrier
+    const int ol = threadIdx.x % out, s = threadIdx.x / out;
+    const int o = yg * out + ol;
+    const bool f64 = bd.fmt == F64 || sizeof(AT) == 8;
+    if (o < total) {
+        const double* src = kp.partial + bd.s_off * nrhs + o;
+        const int n = bd.sleaves;
+        double acc_d = 0.0;
+        AT acc_a = AT(0);
+        int l = s;
+        for (; l + 7 * sl < n; l += 8 * sl) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = src[int64_t(l + q * sl) * total];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (f64) acc_d += v[q];
+                else acc_a += AT(v[q]);
+            }
+        }
+        for (; l < n; l += sl) {
+            if (f64) acc_d += src[int64_t(l) * total];
+            else acc_a += AT(src[int64_t(l) * total]);
+        }
+        sred[threadIdx.x] = f64 ? acc_d : double(acc_a);
+    }
+    __syncthreads();
+    if (s == 0 && o < total) {
+        double r;
+        if (f64) {
+            double a = sred[ol];
+            for (int q = 1; q < sl; ++q) a += sred[q * out + ol];
+            r = a;
+        } else {
+            AT a = AT(sred[ol]);
+            for (int q = 1; q < sl; ++q) a += AT(sred[q * out + ol]);
+            r = double(a);
+        }
+        kp.T[bd.t_off * nrhs + o] = r * kp.tscale[bd.ts_off + o / nrhs];
+    }
+    __syncthreads();                                    // sred is reused by the next work item
+}
+
+// The contraction and the reduction of an operator: stacked (kp.stacked,
+// work unit = SUnit, partials per leaf) or by items (work unit = CItem,
+// partials per item).
+// (a template parameter, not a run-time branch: one kernel holding both
+// would take the larger register count for both)
+template <typename XT, typename AT, int NT, bool STACK>
+__device__ void run_contract_w(const KParams& kp, int unit, int yg, const XT* __restrict__ Xc, int64_t ldc,
+                               int nrhs, double* smem_d) {
+    if constexpr (STACK)
+        run_contract_stack<XT, AT, NT>(kp, unit, yg, Xc, ldc, nrhs, smem_d);
+    else
+        run_contract_items<XT, AT, NT>(kp, unit, yg, Xc, ldc, nrhs, smem_d);
+}
+
+template <typename AT, bool STACK>
+__device__ void run_reduce_w(const KParams& kp, int block, int yg, int nrhs) {
+    if constexpr (STACK)
+        run_reduce_stack<AT>(kp, block, yg, nrhs);
+    else
+        run_reduce_items<AT>(kp, block, yg, nrhs);
+}
+
+template <typename XT, typename AT, int NT, bool STACK>
+__global__ __launch_bounds__(kThreads) void k_contract_w(KParams kp, const XT* __restrict__ Xc, int64_t ldc,
+                                                         int nrhs) {
+    extern __shared__ double smem_d[];
+    run_contract_w<XT, AT, NT, STACK>(kp, blockIdx.x, blockIdx.y, Xc, ldc, nrhs, smem_d);
+}
+
+// reduction by items: blockIdx.x the block, blockIdx.y its 256-output chunk
+template <typename AT>
+__global__ __launch_bounds__(256) void k_reduce_items(KParams kp, int nrhs) {
+    run_reduce_items<AT>(kp, blockIdx.x, blockIdx.y, nrhs);
+}
+
+// Launch shape of the reduction of one product: levels one after another,
+// level k holding 2^k blocks x chunks[k - 1] chunks (its largest rank x
+// nrhs outputs in chunks of 256 / stack_slices(2^(depth - k))), from
+// workgroup start[k - 1] on.
+struct ReduceShape {
+    int32_t depth;
+    int32_t start[kMaxDepth + 1];
+    int32_t chunks[kMaxDepth];
+};
+
+template <typename AT>
+__global__ __launch_bounds__(256) void k_reduce_stack(KParams kp, int nrhs, ReduceShape rs) {
+    const int w = blockIdx.x;
+    int k = 1;
+    while (k < rs.depth && w >= rs.start[k]) ++k;
+    const int rem = w - rs.start[k - 1];
+    run_reduce_stack<AT>(kp, (1 << k) - 2 + rem / rs.chunks[k - 1], rem % rs.chunks[k - 1], nrhs);
 }
 
 // rows [j0, j0 + rows) of T_b (stored [j][c], ld nrhs) for right-hand
@@ -648,15 +890,35 @@ hipError_t launch_wide_nt(const KParams& kp, const XT* Xw, int64_t ldw, XT* Y, i
     hipStream_t s = tm.s;
     constexpr int NTC = NT > 4 ? 4 : NT;                // contraction: at most 64 columns per workgroup
     constexpr int CW = 16 * NT;
-    if (kp.ncitems > 0) {
+    if (kp.ncitems > 0) {                               // some block has a nonzero rank
+        const int gy = (nrhs + 16 * NTC - 1) / (16 * NTC);
         tm.begin(1);
-        hipLaunchKernelGGL((k_contract_w<XT, AT, NTC>), dim3(kp.ncitems, (nrhs + 16 * NTC - 1) / (16 * NTC)),
-                           dim3(kThreads), size_t(kWaves) * NTC * 256 * sizeof(double), s, kp, Xw, ldw, nrhs);
+        const size_t lds_c = size_t(kWaves) * NTC * 256 * sizeof(double);
+        if (kp.stacked)
+            hipLaunchKernelGGL((k_contract_w<XT, AT, NTC, true>), dim3(kp.nsunits, gy), dim3(kThreads), lds_c, s, kp,
+                               Xw, ldw, nrhs);
+        else
+            hipLaunchKernelGGL((k_contract_w<XT, AT, NTC, false>), dim3(kp.ncitems, gy), dim3(kThreads), lds_c, s, kp,
+                               Xw, ldw, nrhs);
         tm.end(1);
-        // largest rank * nrhs of a block bounds the outputs per block
         tm.begin(3);
-        const int64_t rows_y = (int64_t(kp.max_block_rank) * nrhs + 255) / 256;
-        hipLaunchKernelGGL((k_reduce_w<AT>), dim3(kp.nblocks, unsigned(rows_y)), dim3(256), 0, s, kp, nrhs);
+        if (kp.stacked) {
+            ReduceShape rs{};
+            rs.depth = kp.depth;
+            int64_t nwg = 0;
+            for (int k = 1; k <= kp.depth; ++k) {
+                const int out = 256 / stack_slices(1 << (kp.depth - k));
+                rs.start[k - 1] = int32_t(nwg);
+                rs.chunks[k - 1] = std::max(1, int((int64_t(kp.level_max_rank[k - 1]) * nrhs + out - 1) / out));
+                nwg += (int64_t(1) << k) * rs.chunks[k - 1];
+            }
+            rs.start[kp.depth] = int32_t(nwg);
+            hipLaunchKernelGGL((k_reduce_stack<AT>), dim3(unsigned(nwg)), dim3(256), 0, s, kp, nrhs, rs);
+        } else {
+            // largest rank * nrhs of a block bounds the outputs per block
+            const int64_t rows_y = (int64_t(kp.max_block_rank) * nrhs + 255) / 256;
+            hipLaunchKernelGGL((k_reduce_items<AT>), dim3(kp.nblocks, unsigned(rows_y)), dim3(256), 0, s, kp, nrhs);
+        }
         tm.end(3);
     }
     // LDS: two X steps, then T of all levels if it fits in 64 KB, else T
