@@ -244,7 +244,12 @@ hodlr_status hodlr_get_block(hodlr_op op, int32_t block, hodlr_block_info* info)
 /* Everything about an operator in one call: the hodlr_info fields, the
  * last assignment of every level (format, xi_k, u'_k and the insufficient
  * mark of Alg. "Adaptive-precision HODLR Format"; entries past depth are
- * 0) and whether blocks carry their own formats (HODLR_PER_BLOCK).
+ * 0), whether blocks carry their own formats (HODLR_PER_BLOCK), and which
+ * contraction the matrix-core products run: leaf_stacked = 1 when, for
+ * every leaf, the ranks of all its ancestor blocks (one per level) fit one
+ * pass of stacked 16-row matrix-core tiles of one format (at most 64
+ * rows, 32 with fp64 arithmetic), so T_b = V_b^T X is formed leaf by leaf
+ * with X read once; 0 when it is formed per level over runs of rows.
  * leaf_bounds: NULL, or room for 2^depth + 1 values (leaf node boundaries,
  * Def. 2.1); ranks: NULL, or room for nblocks values (canonical order). */
 #define HODLR_MAX_LEVELS 24
@@ -255,7 +260,7 @@ typedef struct {
     double xi[HODLR_MAX_LEVELS];
     double u_prime[HODLR_MAX_LEVELS];
     int32_t per_block;
-    int32_t reserved_;
+    int32_t leaf_stacked;
 } hodlr_query_info;
 
 hodlr_status hodlr_query(hodlr_op op, hodlr_query_info* q, int64_t* leaf_bounds, int32_t* ranks);

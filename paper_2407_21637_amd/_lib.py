@@ -82,7 +82,7 @@ class LuReport(C.Structure):
 class QueryInfo(C.Structure):
     _fields_ = [("info", Info), ("level_dtype", C.c_int32 * MAX_LEVELS), ("insufficient", C.c_int32 * MAX_LEVELS),
                 ("xi", C.c_double * MAX_LEVELS), ("u_prime", C.c_double * MAX_LEVELS),
-                ("per_block", C.c_int32), ("reserved_", C.c_int32)]
+                ("per_block", C.c_int32), ("leaf_stacked", C.c_int32)]
 
 
 class BlockInfo(C.Structure):
@@ -288,6 +288,7 @@ class Operator:
         d["levels"] = [(DTYPE_NAMES[q.level_dtype[k]], q.xi[k], q.u_prime[k], bool(q.insufficient[k]))
                        for k in range(L)]
         d["per_block"] = bool(q.per_block)
+        d["leaf_stacked"] = bool(q.leaf_stacked)
         d["leaf_bounds"] = lb
         d["ranks"] = rk[:self.nblocks]
         return d

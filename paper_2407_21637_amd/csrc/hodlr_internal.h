@@ -171,7 +171,7 @@ struct KParams {
     int32_t nleaves;
     int32_t ncitems;
     int32_t nsunits;
-    int32_t stacked;             // matrix-core contraction by stacked tiles (SUnit) instead of items
+    int32_t stacked;             // matrix-core contraction by stacked tiles (SUnit): the most tiles of a unit; 0: by items
     int32_t netiles;
     int32_t padded;              // 1 if any leaf has padding rows (X goes through xpad)
     int32_t max_block_rank;      // largest rank of a block

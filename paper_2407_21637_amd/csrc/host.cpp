@@ -277,7 +277,7 @@ struct hodlr_op_s {
     std::vector<ETile> etiles;
     int64_t fac_bytes = 0;     // device factor buffer size
     int64_t total_rank = 0;    // sum of ranks (T slots)
-    int64_t total_rank32 = 0;  // sum of ranks rounded up to 32 (T slots in a low working precision)
+    int64_t total_rank8 = 0;   // sum of ranks rounded up to 8 (T slots in a low working precision)
     int64_t total_item_rank = 0;
     std::vector<STile> stiles;                 // matrix-core contraction tiles (see stack_tiles)
     std::vector<int32_t> stile_off;            // per leaf, nleaves + 1
@@ -609,7 +609,7 @@ hodlr_status pack(hodlr_op_s* op) {
         d.t_off = toff;
         toff += p;
         d.tw_off = twoff;
-        twoff += (p + 31) / 32 * 32;
+        twoff += (p + 7) / 8 * 8;
         d.ts_off = ts_total;
         ts_off[b] = ts_total;
         ts_total += p;
@@ -634,7 +634,7 @@ hodlr_status pack(hodlr_op_s* op) {
     stack_tiles(op);
     op->fac_bytes = std::max<int64_t>(off, kPanelAlign);
     op->total_rank = toff;
-    op->total_rank32 = twoff;
+    op->total_rank8 = twoff;
     op->total_item_rank = poff;
     op->max_items_rank = 0;
     for (int b = 0; b < nb; ++b)
@@ -1134,6 +1134,7 @@ hodlr_status hodlr_query(hodlr_op op, hodlr_query_info* q, int64_t* leaf_bounds,
         q->u_prime[k] = op->uprime[k];
     }
     q->per_block = op->block_fmt.empty() ? 0 : 1;
+    q->leaf_stacked = op->stacked ? 1 : 0;
     if (leaf_bounds) {
         const int64_t* lb = op->bounds.data() + ((int64_t(1) << op->depth) - 1) + op->depth;
         std::memcpy(leaf_bounds, lb, sizeof(int64_t) * size_t(op->nleaves + 1));
@@ -1273,14 +1274,16 @@ WsNeeds workspace_needs(const hodlr_op_s* op, int nrhs, int xy_bytes) {
     // which reads X with 16-byte vector loads and copies it when it is not aligned
     // (the low working precision path, 2-byte X, always runs on the matrix cores)
     const bool lowp = xy_bytes == 2;
-    // partials: per contraction item below kWideMin columns, per (block, leaf) at or above
-    n.partial = std::max<int64_t>(1, (nrhs >= kWideMin && !lowp && op->stacked ? op->total_stack_rank
-                                                                                : op->total_item_rank) *
+    // partials: per (block, leaf) for the leaf-stacked contraction (operators
+    // whose leaves are one unit each, on the matrix cores: nrhs >= kWideMin
+    // or the low working precision), else per contraction item
+    n.partial = std::max<int64_t>(1, ((nrhs >= kWideMin || lowp) && op->stacked ? op->total_stack_rank
+                                                                                  : op->total_item_rank) *
                                          nrhs) * 8;
     n.T = std::max<int64_t>(1, op->total_rank * nrhs) * 8;
     n.xpad = (op->padded || nrhs >= kWideMin || lowp) ? op->npad * nrhs * xy_bytes : 0;
     n.W = (nrhs < kWideMin && !lowp) ? op->npad * nrhs * 8 : 0;
-    n.Tw = lowp ? std::max<int64_t>(1, op->total_rank32 * nrhs) * 2 : 0;
+    n.Tw = lowp ? std::max<int64_t>(1, op->total_rank8 * nrhs) * 2 : 0;
     n.sync = sync_words(op->nb) * int64_t(sizeof(int32_t));
     return n;
 }
@@ -1296,7 +1299,9 @@ void fill_kparams(const hodlr_op_s* op, KParams* kp) {
     kp->stile_off = op->d_stile_off;
     kp->sunits = op->d_sunits;
     kp->nsunits = int32_t(op->sunits.size());
-    kp->stacked = op->stacked ? 1 : 0;
+    kp->stacked = 0;
+    if (op->stacked)
+        for (const SUnit& su : op->sunits) kp->stacked = std::max(kp->stacked, su.ng);
     for (int k = 0; k < kMaxDepth; ++k) kp->level_max_rank[k] = 0;
     for (int b = 0; b < op->nb; ++b) {
         const int k = op->bdesc[size_t(b)].level;

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kExpandThreads) void kb_expand(const BatchOp* __res
     }
 }
 
-template <typename XT, typename AT, int NT, bool STACK>
+template <typename XT, typename AT, int NT, int STACK>
 __global__ __launch_bounds__(kThreads) void kb_contract_w(const BatchOp* __restrict__ ops,
                                                           const WorkItem* __restrict__ w, int nw) {
     extern __shared__ double smem_d[];
@@ -122,10 +122,10 @@ hipError_t batch_wide(const BatchGroup& g, hipStream_t s) {
         hipLaunchKernelGGL((kb_padx<XT>), dim3(g.grid[0]), dim3(256), 0, s, g.ops, g.padx, g.n_padx);
     if (g.n_contract) {
         if (g.stacked)
-            hipLaunchKernelGGL((kb_contract_w<XT, AT, NTC, true>), dim3(g.grid[1]), dim3(kThreads),
+            hipLaunchKernelGGL((kb_contract_w<XT, AT, NTC, 4>), dim3(g.grid[1]), dim3(kThreads),
                                size_t(g.lds_contract), s, g.ops, g.contract, g.n_contract);
         else
-            hipLaunchKernelGGL((kb_contract_w<XT, AT, NTC, false>), dim3(g.grid[1]), dim3(kThreads),
+            hipLaunchKernelGGL((kb_contract_w<XT, AT, NTC, 0>), dim3(g.grid[1]), dim3(kThreads),
                                size_t(g.lds_contract), s, g.ops, g.contract, g.n_contract);
     }
     if (g.n_reduce) {

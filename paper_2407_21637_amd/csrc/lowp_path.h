@@ -164,13 +164,13 @@ __global__ __launch_bounds__(kThreads) void k_contract_lp(KParams kp, const W* _
 }
 
 // T_b in W: thread o of block b makes entry (c, j) = (o / P, o % P) of the
-// [c][j] array (P = rank rounded up to 32, zero past the rank), the item
+// [c][j] array (P = rank rounded up to 8, zero past the rank), the item
 // partials summed in fp32 in item order, scaled, rounded once
 template <typename W>
 __global__ __launch_bounds__(256) void k_reduce_lp(KParams kp, int nrhs) {
     const BlockDesc bd = kp.blocks[blockIdx.x];
     const int p = bd.rank;
-    const int P = (p + 31) & ~31;
+    const int P = (p + 7) & ~7;
     const int o = blockIdx.y * 256 + threadIdx.x;
     if (o >= P * nrhs) return;
     const int c = o / P, j = o - (o / P) * P;
@@ -192,6 +192,214 @@ __global__ __launch_bounds__(256) void k_reduce_lp(KParams kp, int nrhs) {
     }
     for (; i < bd.nitems; ++i) s += float(src[int64_t(i) * total]);
     Tw[o] = W(double(s) * kp.tscale[bd.ts_off + j]);     // the scale is a power of two: one rounding
+}
+
+// ---------------------------------------------------------------------------
+// contraction on leaf-stacked tiles (operators whose every leaf is one
+// contraction unit): X read once per leaf for all levels
+// ---------------------------------------------------------------------------
+// The partial T_b of every ancestor block of leaf `leaf` over the leaf's
+// rows, right-hand sides [c0, c0 + 16 NT): the leaf's (block, rank) rows
+// stacked 16 to a tile (STile, ng <= TG tiles of format F), the codes
+// rounded to W as in contract_item_lp, X in W from the 8-row blocked
+// layout.  The waves split the rows in 32-row steps, H steps per pass
+// loaded before any is multiplied (the accumulation order is that of one
+// step per pass); lane group g of a step holds rows 8g..8g+7.  The four
+// waves' blocks are added in LDS and stored in fp32 as the leaf's slice of
+// each block's partials ([j][c], ld nrhs).
+template <int F, typename W, int NT, int TG, int H>
+__device__ void contract_group_lp(const KParams& kp, const LeafDesc& L, int leaf, const STile* __restrict__ tiles,
+                                  int ng, const W* __restrict__ X8, int nrhs, int c0, float* red) {
+    typedef LpMfma<W> M;
+    typedef typename M::v8 V8;
+    constexpr int S = Codec<F>::kBytes;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    // the lane's row of each tile (see contract_group_s): tiles past ng
+    // repeat tile 0 (valid addresses), rows past a tile's n its row 0
+    const uint8_t* vb[TG];
+    int vr0[TG], vch[TG], vrows[TG], vp[TG], vj[TG];
+    bool vok[TG];
+#pragma unroll
+    for (int tg = 0; tg < TG; ++tg) {
+        const int t = tg < ng ? tg : 0;
+        const BlockDesc& bd = kp.blocks[tiles[t].blk[li]];
+        vok[tg] = tg < ng && li < tiles[t].n;
+        vb[tg] = kp.fac + bd.v_off;
+        vr0[tg] = L.prow0 - bd.vrow0;
+        vch[tg] = bd.pad_;
+        vrows[tg] = bd.vrows;
+        vp[tg] = bd.rank;
+        vj[tg] = tiles[t].j[li];
+    }
+    f32x4 acc[TG][NT];
+#pragma unroll
+    for (int a = 0; a < TG; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) zero_acc(acc[a][b]);
+    const V8 zero = {};
+    const int nstep = (L.mp + kStep - 1) / kStep;
+    for (int st = wave; st < nstep; st += H * kWaves) {
+        RawCodes<F, kKL> rv[H][TG];
+        V8 b[H][NT];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const int row = (st + h * kWaves) * kStep + g * kKL;   // mp and row are multiples of 8
+            const bool ok = row < L.mp;
+            const int rowc = ok ? row : 0;
+#pragma unroll
+            for (int tg = 0; tg < TG; ++tg) {
+                const int r = vr0[tg] + rowc;                       // row in the panel
+                const int cs = (r / vch[tg]) * vch[tg];             // its chunk: first row and rows
+                const int rows_c = min(vch[tg], vrows[tg] - cs);
+                rv[h][tg].load(vb[tg] + (int64_t(cs) * vp[tg] + int64_t(vj[tg]) * rows_c + (r - cs)) * S);
+            }
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+                const int c = c0 + 16 * ct + li;
+                b[h][ct] = (ok && c < nrhs) ? load_w8<W>(X8 + (((int64_t(L.prow0) + row) >> 3) * nrhs + c) * 8)
+                                            : zero;
+            }
+        }
+        V8 a[H][TG];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const bool ok = (st + h * kWaves) * kStep + g * kKL < L.mp;
+#pragma unroll
+            for (int tg = 0; tg < TG; ++tg) {
+                CodeT<F> v[kKL];
+                rv[h][tg].template decode<CodeT<F>>(v, ok && vok[tg]);
+#pragma unroll
+                for (int q = 0; q < kKL; ++q) a[h][tg][q] = W(v[q]);
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int tg = 0; tg < TG; ++tg)
+                if (tg < ng)
+#pragma unroll
+                    for (int ct = 0; ct < NT; ++ct) acc[tg][ct] = M::mma(a[h][tg], b[h][ct], acc[tg][ct]);
+    }
+    // add the four waves' blocks, one tile at a time, and store each row's
+    // slice [c][j] (ld rank): the tile rows of one block are consecutive
+    // ranks, so consecutive threads (row fastest) store consecutive words
+    float* part = reinterpret_cast<float*>(kp.partial);
+#pragma unroll
+    for (int tg = 0; tg < TG; ++tg) {
+        if (tg >= ng) break;
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) red[(wave * NT + ct) * 256 + (4 * g + e) * 16 + li] = acc[tg][ct][e];
+        __syncthreads();
+        const int n = tiles[tg].n;
+        for (int idx = threadIdx.x; idx < NT * 256; idx += kThreads) {
+            const int ct = idx >> 8, cl = (idx >> 4) & 15, jr = idx & 15;
+            const int c = c0 + 16 * ct + cl;
+            const int ri = ct * 256 + jr * 16 + cl;
+            float s = 0.0f;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) s += red[(w * NT) * 256 + ri];
+            if (jr < n && c < nrhs) {
+                const BlockDesc& bd = kp.blocks[tiles[tg].blk[jr]];
+                part[(bd.s_off + int64_t(leaf - bd.sleaf0) * bd.rank) * nrhs + int64_t(c) * bd.rank + tiles[tg].j[jr]] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// one contraction unit (blockIdx.x) for right-hand-side group blockIdx.y,
+// at most TGM tiles to a unit (the launch takes 2 when no unit has more,
+// which halves the accumulators); fp64 codes come at most two tiles to a
+// unit, and four loads in flight per lane are enough for 4- and 8-byte codes
+template <typename W, int NT, int TGM>
+__global__ __launch_bounds__(kThreads) void k_contract_lp_stack(KParams kp, const W* __restrict__ X8, int nrhs) {
+    extern __shared__ double smem_d[];
+    const SUnit su = kp.sunits[blockIdx.x];
+    const LeafDesc L = kp.leaves[su.leaf];
+    const STile* tiles = kp.stiles + su.t0;
+    const int c0 = blockIdx.y * 16 * NT;
+    float* red = reinterpret_cast<float*>(smem_d);
+    switch (tiles[0].fmt) {
+        case F64: contract_group_lp<F64, W, NT, 2, 1>(kp, L, su.leaf, tiles, su.ng, X8, nrhs, c0, red); break;
+        case F32: contract_group_lp<F32, W, NT, TGM, 1>(kp, L, su.leaf, tiles, su.ng, X8, nrhs, c0, red); break;
+        case BF16: contract_group_lp<BF16, W, NT, TGM, 2>(kp, L, su.leaf, tiles, su.ng, X8, nrhs, c0, red); break;
+        case F16: contract_group_lp<F16, W, NT, TGM, 2>(kp, L, su.leaf, tiles, su.ng, X8, nrhs, c0, red); break;
+        case E4M3: contract_group_lp<E4M3, W, NT, TGM, 2>(kp, L, su.leaf, tiles, su.ng, X8, nrhs, c0, red); break;
+        default: contract_group_lp<E5M2, W, NT, TGM, 2>(kp, L, su.leaf, tiles, su.ng, X8, nrhs, c0, red); break;
+    }
+}
+
+// Slices of k_reduce_lp_stack at a level of `leaves` leaves per column
+// node and at most pmax ranks per block (<= 64 on a stacked operator):
+// stack_slices(leaves), halved until a slice's 256 / SL threads hold pmax
+// outputs; and the columns of T_b per workgroup, (256 / SL) / pmax.
+__host__ __device__ inline int lp_reduce_slices(int leaves, int pmax) {
+    int sl = stack_slices(leaves);
+    while (sl > 1 && 256 / sl < pmax) sl >>= 1;
+    return sl;
+}
+__host__ __device__ inline int lp_reduce_cols(int sl, int pmax) {
+    const int c = pmax > 0 ? (256 / sl) / pmax : 256 / sl;
+    return c > 1 ? c : 1;
+}
+
+// T_b in W from the per-leaf fp32 partials ([c][j] slices), columns
+// [c0, c0 + cw) of block b per workgroup (launch shape: ReduceShape by
+// columns).  Output v = (c - c0) p + j (j < p) is summed by the threads
+// (v, s), s < SL = lp_reduce_slices(leaves, pmax): slices s, s + SL, ... in order
+// (eight loads issued before their adds), then the SL runs in order; the
+// sum is scaled and rounded once.  The workgroup then writes its columns
+// of the [c][j] array whole (ld P = rank rounded up to 8, zero past the
+// rank), as k_reduce_lp stores it.
+template <typename W>
+__global__ __launch_bounds__(256) void k_reduce_lp_stack(KParams kp, int nrhs, ReduceShape rs) {
+    __shared__ float sred[256];
+    const int w = blockIdx.x;
+    int k = 1;
+    while (k < rs.depth && w >= rs.start[k]) ++k;
+    const int rem = w - rs.start[k - 1];
+    const int yg = rem % rs.chunks[k - 1];
+    const BlockDesc bd = kp.blocks[(1 << k) - 2 + rem / rs.chunks[k - 1]];
+    const int p = bd.rank, P = (p + 7) & ~7;
+    const int pmax = kp.level_max_rank[k - 1];
+    const int sl = lp_reduce_slices(bd.sleaves, pmax), out = 256 / sl;
+    const int cw = lp_reduce_cols(sl, pmax);
+    const int c0 = yg * cw;
+    if (p == 0 || c0 >= nrhs) return;                   // whole workgroup: before the barrier
+    const int ncol = min(cw, nrhs - c0);
+    const int v = threadIdx.x % out, s = threadIdx.x / out;
+    const int valid = p * nrhs;
+    if (v < ncol * p) {                                 // ncol p <= cw pmax <= out
+        const float* src = reinterpret_cast<const float*>(kp.partial) + bd.s_off * nrhs + int64_t(c0) * p + v;
+        const int n = bd.sleaves;
+        float acc = 0.0f;
+        int l = s;
+        for (; l + 7 * sl < n; l += 8 * sl) {
+            float x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = src[int64_t(l + q * sl) * valid];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc += x[q];
+        }
+        for (; l < n; l += sl) acc += src[int64_t(l) * valid];
+        sred[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    W* Tw = static_cast<W*>(kp.Tw) + bd.tw_off * nrhs + int64_t(c0) * P;
+    for (int i = threadIdx.x; i < ncol * P; i += 256) {
+        const int cl = i / P, j = i - cl * P;
+        W r = W(0.0f);
+        if (j < p) {
+            const int vi = cl * p + j;
+            float a = sred[vi];
+            for (int q = 1; q < sl; ++q) a += sred[q * out + vi];
+            r = W(double(a) * kp.tscale[bd.ts_off + j]);    // the scale is a power of two: one rounding
+        }
+        Tw[i] = r;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -348,7 +556,7 @@ __global__ __launch_bounds__(kThreads) void k_expand_lp(KParams kp, const W* __r
         const int k = threadIdx.x + 1;
         const BlockDesc& bd = kp.blocks[(1 << k) - 2 + (t.leaf >> (depth - k))];
         seg_p[k - 1] = bd.rank;
-        seg_t[k - 1] = bd.tw_off * nrhs + int64_t(c0) * ((bd.rank + 31) & ~31);
+        seg_t[k - 1] = bd.tw_off * nrhs + int64_t(c0) * ((bd.rank + 7) & ~7);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -362,7 +570,7 @@ __global__ __launch_bounds__(kThreads) void k_expand_lp(KParams kp, const W* __r
     __syncthreads();
     // stage T_b of the leaf's ancestors: ts[c][seg_k + j] = T_b[c0 + c][j], zero past the rank / nrhs / kp,
     // in 16-byte chunks (a segment is round_up(p, 8) wide and T_b is stored zero from p up to a multiple
-    // of 32, so a chunk never crosses a column); each thread issues its loads before it stores any
+    // of 8, so a chunk never crosses a column); each thread issues its loads before it stores any
     {
         typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
         constexpr int kB = 4;
@@ -383,7 +591,7 @@ __global__ __launch_bounds__(kThreads) void k_expand_lp(KParams kp, const W* __r
                         const int j = kk - seg_k[k - 1];
                         const int p = seg_p[k - 1];
                         if (j < p)
-                            v[i] = *reinterpret_cast<const u32x4*>(Tw + seg_t[k - 1] + int64_t(c) * ((p + 31) & ~31) + j);
+                            v[i] = *reinterpret_cast<const u32x4*>(Tw + seg_t[k - 1] + int64_t(c) * ((p + 7) & ~7) + j);
                     }
                 }
             }
@@ -477,13 +685,35 @@ hipError_t launch_lp_nt(const KParams& kp, const W* X8, W* Y, int64_t ldy, int n
     hipStream_t s = tm.s;
     const int gy = (nrhs + 16 * NT - 1) / (16 * NT);
     if (kp.ncitems > 0) {
+        const size_t lds_c = size_t(kWaves) * NT * 256 * sizeof(float);
         tm.begin(1);
-        hipLaunchKernelGGL((k_contract_lp<W, NT>), dim3(kp.ncitems, gy), dim3(kThreads),
-                           size_t(kWaves) * NT * 256 * sizeof(float), s, kp, X8, nrhs);
+        if (kp.stacked > 2)
+            hipLaunchKernelGGL((k_contract_lp_stack<W, NT, 4>), dim3(kp.nsunits, gy), dim3(kThreads), lds_c, s, kp,
+                               X8, nrhs);
+        else if (kp.stacked)
+            hipLaunchKernelGGL((k_contract_lp_stack<W, NT, 2>), dim3(kp.nsunits, gy), dim3(kThreads), lds_c, s, kp,
+                               X8, nrhs);
+        else
+            hipLaunchKernelGGL((k_contract_lp<W, NT>), dim3(kp.ncitems, gy), dim3(kThreads), lds_c, s, kp, X8, nrhs);
         tm.end(1);
         tm.begin(3);
-        const int64_t rows_y = (int64_t((kp.max_block_rank + 31) & ~31) * nrhs + 255) / 256;
-        hipLaunchKernelGGL((k_reduce_lp<W>), dim3(kp.nblocks, unsigned(rows_y)), dim3(256), 0, s, kp, nrhs);
+        if (kp.stacked) {
+            ReduceShape rs{};
+            rs.depth = kp.depth;
+            int64_t nwg = 0;
+            for (int k = 1; k <= kp.depth; ++k) {           // chunks of lp_reduce_cols columns
+                const int pmax = kp.level_max_rank[k - 1];
+                const int cw = lp_reduce_cols(lp_reduce_slices(1 << (kp.depth - k), pmax), pmax);
+                rs.start[k - 1] = int32_t(nwg);
+                rs.chunks[k - 1] = (nrhs + cw - 1) / cw;
+                nwg += (int64_t(1) << k) * rs.chunks[k - 1];
+            }
+            rs.start[kp.depth] = int32_t(nwg);
+            hipLaunchKernelGGL((k_reduce_lp_stack<W>), dim3(unsigned(nwg)), dim3(256), 0, s, kp, nrhs, rs);
+        } else {
+            const int64_t rows_y = (int64_t((kp.max_block_rank + 7) & ~7) * nrhs + 255) / 256;
+            hipLaunchKernelGGL((k_reduce_lp<W>), dim3(kp.nblocks, unsigned(rows_y)), dim3(256), 0, s, kp, nrhs);
+        }
         tm.end(3);
     }
     tm.begin(2);

@@ -217,8 +217,10 @@ __device__ void contract_group_dispatch(int fmt, const KParams& kp, const LeafDe
     }
 }
 
-// One contraction unit (a group of tiles of one leaf) for right-hand-side group yg.
-template <typename XT, typename AT, int NT>
+// One contraction unit (a group of tiles of one leaf) for right-hand-side
+// group yg; at most TGM tiles to a unit in fp32 arithmetic (2 when no unit
+// has more, which halves the accumulators), 2 in fp64.
+template <typename XT, typename AT, int NT, int TGM>
 __device__ void run_contract_stack(const KParams& kp, int unit, int yg, const XT* __restrict__ Xc, int64_t ldc,
                                int nrhs, double* smem_d) {
     const SUnit su = kp.sunits[unit];
@@ -230,7 +232,7 @@ __device__ void run_contract_stack(const KParams& kp, int unit, int yg, const XT
         contract_group_dispatch<double, XT, NT, 2>(fmt, kp, L, su.leaf, tiles, su.ng, Xc, ldc, nrhs, c0,
                                                    reinterpret_cast<double*>(smem_d));
     } else if constexpr (sizeof(AT) == 4) {
-        contract_group_dispatch<float, XT, NT, 4>(fmt, kp, L, su.leaf, tiles, su.ng, Xc, ldc, nrhs, c0,
+        contract_group_dispatch<float, XT, NT, TGM>(fmt, kp, L, su.leaf, tiles, su.ng, Xc, ldc, nrhs, c0,
                                                   reinterpret_cast<float*>(smem_d));
     }
 }
@@ -444,15 +446,16 @@ __device__ void run_reduce_stack(const KParams& kp, int block, int yg, int nrhs)
 }
 
 // The contraction and the reduction of an operator: stacked (kp.stacked,
-// work unit = SUnit, partials per leaf) or by items (work unit = CItem,
+// work unit = SUnit, partials per leaf; STACK = the most tiles of a unit
+// the kernel holds, 2 or 4) or by items (STACK = 0, work unit = CItem,
 // partials per item).
 // (a template parameter, not a run-time branch: one kernel holding both
 // would take the larger register count for both)
-template <typename XT, typename AT, int NT, bool STACK>
+template <typename XT, typename AT, int NT, int STACK>
 __device__ void run_contract_w(const KParams& kp, int unit, int yg, const XT* __restrict__ Xc, int64_t ldc,
                                int nrhs, double* smem_d) {
-    if constexpr (STACK)
-        run_contract_stack<XT, AT, NT>(kp, unit, yg, Xc, ldc, nrhs, smem_d);
+    if constexpr (STACK > 0)
+        run_contract_stack<XT, AT, NT, STACK>(kp, unit, yg, Xc, ldc, nrhs, smem_d);
     else
         run_contract_items<XT, AT, NT>(kp, unit, yg, Xc, ldc, nrhs, smem_d);
 }
@@ -465,7 +468,7 @@ __device__ void run_reduce_w(const KParams& kp, int block, int yg, int nrhs) {
         run_reduce_items<AT>(kp, block, yg, nrhs);
 }
 
-template <typename XT, typename AT, int NT, bool STACK>
+template <typename XT, typename AT, int NT, int STACK>
 __global__ __launch_bounds__(kThreads) void k_contract_w(KParams kp, const XT* __restrict__ Xc, int64_t ldc,
                                                          int nrhs) {
     extern __shared__ double smem_d[];
@@ -487,6 +490,21 @@ struct ReduceShape {
     int32_t start[kMaxDepth + 1];
     int32_t chunks[kMaxDepth];
 };
+
+// The shape for a product with nrhs columns.  Returns the workgroups.
+inline int64_t reduce_shape(const KParams& kp, int nrhs, ReduceShape* rs) {
+    *rs = ReduceShape{};
+    rs->depth = kp.depth;
+    int64_t nwg = 0;
+    for (int k = 1; k <= kp.depth; ++k) {
+        const int out = 256 / stack_slices(1 << (kp.depth - k));
+        rs->start[k - 1] = int32_t(nwg);
+        rs->chunks[k - 1] = std::max(1, int((int64_t(kp.level_max_rank[k - 1]) * nrhs + out - 1) / out));
+        nwg += (int64_t(1) << k) * rs->chunks[k - 1];
+    }
+    rs->start[kp.depth] = int32_t(nwg);
+    return nwg;
+}
 
 template <typename AT>
 __global__ __launch_bounds__(256) void k_reduce_stack(KParams kp, int nrhs, ReduceShape rs) {
@@ -891,28 +909,27 @@ hipError_t launch_wide_nt(const KParams& kp, const XT* Xw, int64_t ldw, XT* Y, i
     constexpr int NTC = NT > 4 ? 4 : NT;                // contraction: at most 64 columns per workgroup
     constexpr int CW = 16 * NT;
     if (kp.ncitems > 0) {                               // some block has a nonzero rank
-        const int gy = (nrhs + 16 * NTC - 1) / (16 * NTC);
+        // the stacked contraction with at most two tiles to a unit takes 32
+        // columns per workgroup: twice the workgroups of 64 at four waves
+        // per SIMD instead of two
+        constexpr int NTS = NTC > 2 ? 2 : NTC;
+        const int gy = (nrhs + 16 * NTC - 1) / (16 * NTC), gys = (nrhs + 16 * NTS - 1) / (16 * NTS);
         tm.begin(1);
         const size_t lds_c = size_t(kWaves) * NTC * 256 * sizeof(double);
-        if (kp.stacked)
-            hipLaunchKernelGGL((k_contract_w<XT, AT, NTC, true>), dim3(kp.nsunits, gy), dim3(kThreads), lds_c, s, kp,
+        if (kp.stacked > 2)
+            hipLaunchKernelGGL((k_contract_w<XT, AT, NTC, 4>), dim3(kp.nsunits, gy), dim3(kThreads), lds_c, s, kp,
+                               Xw, ldw, nrhs);
+        else if (kp.stacked)
+            hipLaunchKernelGGL((k_contract_w<XT, AT, NTS, 2>), dim3(kp.nsunits, gys), dim3(kThreads), lds_c, s, kp,
                                Xw, ldw, nrhs);
         else
-            hipLaunchKernelGGL((k_contract_w<XT, AT, NTC, false>), dim3(kp.ncitems, gy), dim3(kThreads), lds_c, s, kp,
+            hipLaunchKernelGGL((k_contract_w<XT, AT, NTC, 0>), dim3(kp.ncitems, gy), dim3(kThreads), lds_c, s, kp,
                                Xw, ldw, nrhs);
         tm.end(1);
         tm.begin(3);
         if (kp.stacked) {
-            ReduceShape rs{};
-            rs.depth = kp.depth;
-            int64_t nwg = 0;
-            for (int k = 1; k <= kp.depth; ++k) {
-                const int out = 256 / stack_slices(1 << (kp.depth - k));
-                rs.start[k - 1] = int32_t(nwg);
-                rs.chunks[k - 1] = std::max(1, int((int64_t(kp.level_max_rank[k - 1]) * nrhs + out - 1) / out));
-                nwg += (int64_t(1) << k) * rs.chunks[k - 1];
-            }
-            rs.start[kp.depth] = int32_t(nwg);
+            ReduceShape rs;
+            const int64_t nwg = reduce_shape(kp, nrhs, &rs);
             hipLaunchKernelGGL((k_reduce_stack<AT>), dim3(unsigned(nwg)), dim3(256), 0, s, kp, nrhs, rs);
         } else {
             // largest rank * nrhs of a block bounds the outputs per block

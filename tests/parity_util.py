@@ -61,6 +61,40 @@ class Case:
                           T.node_bounds(self.n, self.depth, self.leaf_bounds)[self.depth])
 
 
+class RandomCase(Case):
+    """Random factors with a chosen rank per level over the oracle's
+    partition (no compression), for the kernels' rank-dependent paths:
+    U_b, V_b with N(0, 1) entries (U_b scaled by 1/sqrt(rows)), leaves
+    I + N(0, 1/m)."""
+
+    def __init__(self, n, depth, ranks_per_level, seed=0):
+        from types import SimpleNamespace
+        rng = np.random.default_rng(seed)
+        self.cfg = None
+        self.n, self.depth, self.eps, self.leaf_bounds = n, depth, 0.0, None
+        self.blocks = T.blocks(n, depth)
+        self.leaves_b = T.leaves(n, depth)
+        U = [rng.standard_normal((b.nrows, ranks_per_level[b.level - 1])) / np.sqrt(max(b.nrows, 1))
+             for b in self.blocks]
+        V = [rng.standard_normal((b.ncols, ranks_per_level[b.level - 1])) for b in self.blocks]
+        leaves = [np.eye(m) + rng.standard_normal((m, m)) / np.sqrt(max(m, 1)) for _, m in self.leaves_b]
+        self.op = SimpleNamespace(leaves=leaves, U=U, V=V, ranks=[u.shape[1] for u in U])
+        self.norms2 = None
+
+
+# (format, ranks per level, accumulation flag): operators whose every leaf's
+# ancestor ranks fit one pass of stacked 16-row tiles, 1 to 4 tiles per leaf
+STACKED_CASES = [
+    ("e4m3", [16, 16, 16, 16], 0x2),     # four tiles
+    ("e5m2", [5, 4, 4, 3], 0x2),         # one
+    ("bf16", [12, 12, 12, 12], 0x2),     # three
+    ("fp16", [9, 9, 9, 8], 0x2),         # three, a partial last tile
+    ("fp32", [16, 16, 16, 16], 0x2),     # four, fp32 sums
+    ("fp32", [8, 8, 8, 8], 0x4),         # two, fp64 sums
+    ("fp64", [8, 8, 8, 8], 0x2),         # two, fp64 arithmetic
+]
+
+
 def check(y_gpu, y_ora, z, M, acc, xy, label=""):
     """Assert both componentwise gates; return error statistics.
 

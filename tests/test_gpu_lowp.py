@@ -16,7 +16,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from tests.parity_util import Case  # noqa: E402
+from tests.parity_util import STACKED_CASES, Case, RandomCase  # noqa: E402
 from oracle import bounds as BD  # noqa: E402
 from oracle import formats as F  # noqa: E402
 from oracle import lowp as LP  # noqa: E402
@@ -91,6 +91,19 @@ def test_low_accuracy_e4m3_recipe(w, nrhs):
     h.assign_precision(case.eps, case.cfg.allowed, case.norms2)
     fm = [lv[0] for lv in h.levels()]
     _run(case, h, fm, nrhs, w, "c3_s")
+
+
+@pytest.mark.parametrize("fmt,ranks,flags", STACKED_CASES)
+def test_leaf_stacked_contraction(fmt, ranks, flags):
+    """The contraction on leaf-stacked tiles (k_contract_lp_stack and
+    k_reduce_lp_stack): every code format, 1 to 4 tiles per leaf, ragged
+    leaves, 1, 3 and 8 column groups."""
+    case = RandomCase(3000, 4, ranks, seed=5)
+    h = case.library_op()
+    h.set_level_precisions([fmt] * 4, flags)
+    assert h.query()["leaf_stacked"]
+    for w, nrhs in (("bf16", 5), ("fp16", 40), ("bf16", 128)):
+        _run(case, h, [fmt] * 4, nrhs, w, f"stacked-{fmt}")
 
 
 @pytest.mark.parametrize("w", ["bf16", "fp16"])

@@ -18,7 +18,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from tests.parity_util import Case, check  # noqa: E402
+from tests.parity_util import STACKED_CASES, Case, RandomCase, check  # noqa: E402
 from oracle import bounds as BD  # noqa: E402
 from oracle import quantize as Q  # noqa: E402
 
@@ -162,6 +162,24 @@ def test_forced_format_every_level(fmt):
         assert np.array_equal(uc, qu.codes) and np.array_equal(ue, qu.exps)
     for nrhs in (1, 4, 24):
         _run(case, h, [fmt] * case.depth, nrhs, "fp32", "fp32", f"forced-{fmt}")
+
+
+@pytest.mark.parametrize("fmt,ranks,flags", STACKED_CASES)
+def test_leaf_stacked_contraction_matrix_cores(fmt, ranks, flags):
+    """The matrix-core contraction on leaf-stacked tiles (k_contract_w and
+    k_reduce_stack): every code format, 1 to 4 tiles per leaf, fp32 and
+    fp64 sums, ragged leaves, fp32 and fp64 X."""
+    case = RandomCase(3000, 4, ranks, seed=6)
+    h = case.library_op()
+    h.set_level_precisions([fmt] * 4, flags)
+    assert h.query()["leaf_stacked"]
+    acc = "fp64" if flags == H.ACC_FP64 else "fp32"
+    rng = np.random.default_rng(8)
+    for xy, nrhs in (("fp32", 8), ("fp32", 40), ("fp64", 16)):
+        X = rng.standard_normal((case.n, nrhs))
+        if xy == "fp32":
+            X = X.astype(np.float32).astype(np.float64)
+        _run(case, h, [fmt] * 4, nrhs, xy, acc, f"stacked-{fmt}", X=X)
 
 
 def test_mixed_formats_and_fp64_accumulation():

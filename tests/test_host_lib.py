@@ -335,3 +335,37 @@ def test_binding_refuses_mismatched_tensors():
     from paper_2407_21637_amd._lib import _xy_code
     assert [_xy_code(torch.zeros(1, dtype=d)) for d in
             (torch.float64, torch.float32, torch.bfloat16, torch.float16)] == [0, 1, 2, 3]
+
+
+def _ranked_op(n, depth, ranks_per_level, seed=0):
+    """A host-only operator with random factors of the given rank per level."""
+    rng = np.random.default_rng(seed)
+    blks = T.blocks(n, depth)
+    U = [rng.standard_normal((b.nrows, ranks_per_level[b.level - 1])) for b in blks]
+    V = [rng.standard_normal((b.ncols, ranks_per_level[b.level - 1])) for b in blks]
+    leaves = [rng.standard_normal((m, m)) for _, m in T.leaves(n, depth)]
+    return H.Operator(n, depth, leaves, U, V, device=-1)
+
+
+@pytest.mark.parametrize("ranks,fmts,flags,stacked", [
+    # one format: every leaf's ancestor ranks in 16-row tiles, at most 4 (fp32 sums) or 2 (fp64)
+    ([5, 4, 4, 3], ["e4m3"] * 4, H.ACC_FP32, True),
+    ([16, 16, 16, 16], ["bf16"] * 4, H.ACC_FP32, True),           # 64 rows: four tiles
+    ([16, 16, 16, 17], ["bf16"] * 4, H.ACC_FP32, False),          # 65 rows: five
+    ([8, 8, 8, 8], ["fp32"] * 4, H.ACC_FP64, True),               # fp64 sums: two tiles
+    ([9, 8, 8, 8], ["fp32"] * 4, H.ACC_FP64, False),
+    ([8, 8, 8, 8], ["fp64"] * 4, H.ACC_FP32, True),               # fp64 codes: fp64 arithmetic
+    ([8, 8, 8, 9], ["fp64"] * 4, H.ACC_FP32, False),
+    # two formats on a leaf: two units
+    ([3, 3, 3, 3], ["e4m3", "e4m3", "e5m2", "e4m3"], H.ACC_FP32, False),
+    ([3, 3, 3, 3], ["fp64", "fp32", "fp32", "fp32"], H.ACC_FP32, False),
+    # a zero rank everywhere: no tiles at all
+    ([0, 0, 0, 0], ["fp32"] * 4, H.ACC_FP32, False),
+])
+def test_leaf_stacked_contraction_rule(ranks, fmts, flags, stacked):
+    """hodlr_query's leaf_stacked: each leaf's (block, rank) rows of all
+    levels, grouped by format and arithmetic type 16 to a tile, must make a
+    single group of at most 4 tiles (2 with fp64 arithmetic)."""
+    h = _ranked_op(1000, 4, ranks)
+    h.set_level_precisions(fmts, flags)
+    assert h.query()["leaf_stacked"] is stacked
