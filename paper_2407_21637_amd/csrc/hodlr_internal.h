@@ -72,7 +72,7 @@ struct BlockDesc {        // one per off-diagonal block, canonical order
     int32_t nitems;       // number of contraction items
     int32_t pad_;         // rows of a contraction item (V panel chunk)
     int64_t tw_off;       // low working precision: offset of T_b in W, in units of
-                          // round_up(rank, 32) (x nrhs values, [c][j])
+                          // round_up(rank, 8) (x nrhs values, [c][j])
     int64_t s_off;        // matrix-core contraction: per-leaf partials of T_b, offset in units
                           // of rank (x nrhs doubles), one rank x nrhs slice per leaf of the
                           // column node

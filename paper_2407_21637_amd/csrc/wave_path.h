@@ -288,8 +288,9 @@ __device__ void run_leaf(const KParams& kp, int tile, const XT* __restrict__ X, 
 // loads a wave walks is about (sum of the ranks) / (kUnroll x waves) long.
 // A unit's kUnroll column loads are all issued before its FMAs.  Each wave
 // accumulates its units into per-row partials; the waves' partials are
-// added in LDS in wave order, W is added and Y is written once (the order
-// of every sum is fixed, so the result is deterministic).
+// added in LDS in wave order, W (loaded before the units) is added and Y is
+// written once (the order of every sum is fixed, so the result is
+// deterministic).
 constexpr int kExpandWaves = 8;
 constexpr int kExpandThreads = 64 * kExpandWaves;
 
@@ -349,6 +350,7 @@ template <typename XT, typename AT, int RG, int RPL>
 __device__ void run_expand(const KParams& kp, int tile, XT* __restrict__ Y, int64_t ldy, int nrhs,
                            unsigned char* smem, int* s_off) {
     constexpr int TR = 64 * RPL;                    // rows per tile
+    static_assert(TR <= kExpandThreads, "one Y row per thread");
     const ETile t = kp.etiles[tile];
     const LeafDesc L = kp.leaves[t.leaf];
     const int lane = threadIdx.x & 63;
@@ -383,6 +385,15 @@ __device__ void run_expand(const KParams& kp, int tile, XT* __restrict__ Y, int6
     const int nunits = s_u0[depth];
     AT* red = reinterpret_cast<AT*>(ts + s_off[depth]);
     for (int rb = 0; rb < nrhs; rb += RG) {
+        // the leaf product W of the rows this thread writes, loaded before the units
+        AT wv[RG];
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+            const int lr = t.r0 + int(threadIdx.x);
+            wv[rg] = (int(threadIdx.x) < TR && int(threadIdx.x) < t.nr && lr < L.m && rb + rg < nrhs)
+                         ? AT(kp.W[int64_t(L.prow0) + lr + kp.npad * (rb + rg)])
+                         : AT(0);
+        }
         AT acc[RPL][RG];
 #pragma unroll
         for (int i = 0; i < RPL; ++i)
@@ -428,9 +439,7 @@ __device__ void run_expand(const KParams& kp, int tile, XT* __restrict__ Y, int6
 #pragma unroll
                 for (int w = 1; w < kExpandWaves; ++w) sum += red[w * TR + r];
                 const int lr = t.r0 + r;
-                if (r < t.nr && lr < L.m && rb + rg < nrhs)
-                    Y[L.row0 + lr + ldy * (rb + rg)] =
-                        XT(sum + AT(kp.W[int64_t(L.prow0) + lr + kp.npad * (rb + rg)]));
+                if (r < t.nr && lr < L.m && rb + rg < nrhs) Y[L.row0 + lr + ldy * (rb + rg)] = XT(sum + wv[rg]);
             }
             __syncthreads();
         }
