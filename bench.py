@@ -316,7 +316,10 @@ def roofline_single(w, phases, nrhs, traffic):
             "traffic": traffic, "alg_bytes_per_launch": int(w["first"]), "mean_launch_us": round(us, 2)}
 
 
-def launches(w, ph, nrhs):
+def launches(w, ph, nrhs, tr=None):
+    """Both launches of a product: algorithmic bytes, mean cold duration,
+    achieved GB/s, and the counter traffic of the profiles (tr: the
+    summary's keys, only when its kernel hash matches)."""
     wide = nrhs >= 8
     out = {"first": {"kernel": "k_contract_w" if wide else "k_phase1", "alg_bytes": int(w["first"])},
            "second": {"kernel": "k_expand_w" if wide else "k_expand", "alg_bytes": int(w["second"])}}
@@ -324,6 +327,7 @@ def launches(w, ph, nrhs):
         if ph_name in ph:
             out[key]["mean_us"] = round(ph[ph_name], 2)
             out[key]["achieved_gbs"] = round(out[key]["alg_bytes"] / (ph[ph_name] * 1e-6) / 1e9, 2)
+        out[key]["traffic"] = int(tr.get(f"{key}_launch_bytes", 0)) or None if tr else None
     return out
 
 
@@ -449,6 +453,8 @@ def single_workload(name, nrhs_list, args, flush, torch, H, with_cpu, headline):
     traffic = None
     if tr.get("kernel_sha") == kernel_hash(path) and tr.get("workload") == cfg.name and tr.get("nrhs") == str(n0):
         traffic = int(tr.get("second_launch_bytes" if n0 >= 8 else "first_launch_bytes", 0)) or None
+    else:
+        tr = None
     w = r["w"]
     out = {
         "value": round(w["B"] / (r["cold"] * 1e-3) / 1e9, 2), "unit": "GB/s",
@@ -465,7 +471,7 @@ def single_workload(name, nrhs_list, args, flush, torch, H, with_cpu, headline):
         "kernels_us_warm": {k: round(v, 2) for k, v in r["ph_warm"].items()},
         "roofline": roofline_single(w, r["ph_cold"], n0, traffic),
         "roofline_warm": roofline_single(w, r["ph_warm"], n0, None),
-        "launches": launches(w, r["ph_cold"], n0),
+        "launches": launches(w, r["ph_cold"], n0, tr),
         "storage_ratio": storage_ratio(w["store"]),
     }
     out["roofline"]["timing"] = "cold: 2 GiB read sweep before each product"
@@ -630,7 +636,7 @@ def lowp_workload(state, w, nrhs, args, flush, torch, H):
            "warm_cache_gbs": round(B / (warm * 1e-3) / 1e9, 2),
            "speedup_vs_full_precision_path": round(cold_full / cold, 3),
            "kernels_us_cold": {k: round(v, 2) for k, v in ph.items()}, "roofline": roof}
-    # the oracle's W product on a column sample: the tolerance check
+    # the oracle's W product on every column: the tolerance check
     from oracle import bounds as BD
     from oracle import lowp as LP
     from oracle import quantize as Q
@@ -639,7 +645,7 @@ def lowp_workload(state, w, nrhs, args, flush, torch, H):
     lb = T.leaves(n, cfg.depth)
     QU = [Q.quantize(u, fmts[b.level - 1]) for b, u in zip(oblocks, op.U)]
     QV = [Q.quantize(v, fmts[b.level - 1]) for b, v in zip(oblocks, op.V)]
-    k = min(nrhs, 4)
+    k = nrhs
     prod = LP.matvec_lowp(n, oblocks, lb, op.leaves, QU, QV, Xw[:, :k], w)
     fn()
     torch.cuda.synchronize()
