@@ -94,6 +94,11 @@ STACKED_CASES = [
     ("fp64", [8, 8, 8, 8], 0x2),         # two, fp64 arithmetic
 ]
 
+# depth 7, 3072 rows (leaves of 24 rows): level 1's 40 ranks over the 64
+# leaves of its column node exceed the 32 outputs a slice of the bf16
+# reduction's 8 interleaved slices would hold, so it takes fewer slices
+DEEP_STACKED = (3072, 7, [40, 3, 3, 3, 3, 3, 3])
+
 
 def check(y_gpu, y_ora, z, M, acc, xy, label=""):
     """Assert both componentwise gates; return error statistics.

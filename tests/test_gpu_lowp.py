@@ -16,7 +16,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from tests.parity_util import STACKED_CASES, Case, RandomCase  # noqa: E402
+from tests.parity_util import DEEP_STACKED, STACKED_CASES, Case, RandomCase  # noqa: E402
 from oracle import bounds as BD  # noqa: E402
 from oracle import formats as F  # noqa: E402
 from oracle import lowp as LP  # noqa: E402
@@ -104,6 +104,18 @@ def test_leaf_stacked_contraction(fmt, ranks, flags):
     assert h.query()["leaf_stacked"]
     for w, nrhs in (("bf16", 5), ("fp16", 40), ("bf16", 128)):
         _run(case, h, [fmt] * 4, nrhs, w, f"stacked-{fmt}")
+
+
+def test_leaf_stacked_contraction_deep_tree():
+    """A level whose rank exceeds what the reduction's slices hold at that
+    many leaves (fewer slices), four tiles per leaf, ragged small leaves."""
+    n, depth, ranks = DEEP_STACKED
+    case = RandomCase(n, depth, ranks, seed=9)
+    h = case.library_op()
+    h.set_level_precisions(["bf16"] * depth, H.ACC_FP32)
+    assert h.query()["leaf_stacked"]
+    for w, nrhs in (("bf16", 3), ("fp16", 70)):
+        _run(case, h, ["bf16"] * depth, nrhs, w, "stacked-deep")
 
 
 @pytest.mark.parametrize("w", ["bf16", "fp16"])

@@ -18,7 +18,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from tests.parity_util import STACKED_CASES, Case, RandomCase, check  # noqa: E402
+from tests.parity_util import DEEP_STACKED, STACKED_CASES, Case, RandomCase, check  # noqa: E402
 from oracle import bounds as BD  # noqa: E402
 from oracle import quantize as Q  # noqa: E402
 
@@ -180,6 +180,18 @@ def test_leaf_stacked_contraction_matrix_cores(fmt, ranks, flags):
         if xy == "fp32":
             X = X.astype(np.float32).astype(np.float64)
         _run(case, h, [fmt] * 4, nrhs, xy, acc, f"stacked-{fmt}", X=X)
+
+
+def test_leaf_stacked_contraction_deep_tree():
+    """Depth 7 with a large top-level rank: many leaves per column node and
+    four stacked tiles per leaf on the matrix cores."""
+    n, depth, ranks = DEEP_STACKED
+    case = RandomCase(n, depth, ranks, seed=10)
+    h = case.library_op()
+    h.set_level_precisions(["e4m3"] * depth, H.ACC_FP32)
+    assert h.query()["leaf_stacked"]
+    X = np.random.default_rng(11).standard_normal((n, 40)).astype(np.float32).astype(np.float64)
+    _run(case, h, ["e4m3"] * depth, 40, "fp32", "fp32", "stacked-deep", X=X)
 
 
 def test_mixed_formats_and_fp64_accumulation():
