@@ -172,6 +172,8 @@ struct KParams {
     int32_t ncitems;
     int32_t nsunits;
     int32_t stacked;             // matrix-core contraction by stacked tiles (SUnit): the most tiles of a unit; 0: by items
+    int32_t part_f32;            // stacked, every tile in fp32 arithmetic: the per-leaf partials are
+                                 // stored as fp32 (their values are fp32 sums), else fp64
     int32_t netiles;
     int32_t padded;              // 1 if any leaf has padding rows (X goes through xpad)
     int32_t max_block_rank;      // largest rank of a block

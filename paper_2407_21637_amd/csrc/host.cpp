@@ -1300,8 +1300,12 @@ void fill_kparams(const hodlr_op_s* op, KParams* kp) {
     kp->sunits = op->d_sunits;
     kp->nsunits = int32_t(op->sunits.size());
     kp->stacked = 0;
+    kp->part_f32 = op->stacked ? 1 : 0;
     if (op->stacked)
-        for (const SUnit& su : op->sunits) kp->stacked = std::max(kp->stacked, su.ng);
+        for (const SUnit& su : op->sunits) {
+            kp->stacked = std::max(kp->stacked, su.ng);
+            if (op->stiles[size_t(su.t0)].dbl) kp->part_f32 = 0;
+        }
     for (int k = 0; k < kMaxDepth; ++k) kp->level_max_rank[k] = 0;
     for (int b = 0; b < op->nb; ++b) {
         const int k = op->bdesc[size_t(b)].level;

@@ -195,8 +195,15 @@ __device__ void contract_group_s(const KParams& kp, const LeafDesc& L, int leaf,
             for (int w = 0; w < kWaves; ++w) s += red[(w * NT) * 256 + idx];
             if (jr < n && c < nrhs) {
                 const BlockDesc& bd = kp.blocks[tiles[tg].blk[jr]];
-                double* part = kp.partial + (bd.s_off + int64_t(leaf - bd.sleaf0) * bd.rank) * nrhs;
-                part[int64_t(tiles[tg].j[jr]) * nrhs + c] = double(s);
+                const int64_t e = (bd.s_off + int64_t(leaf - bd.sleaf0) * bd.rank + tiles[tg].j[jr]) * nrhs + c;
+                if constexpr (sizeof(CT) == 4) {
+                    if (kp.part_f32)
+                        reinterpret_cast<float*>(kp.partial)[e] = s;
+                    else
+                        kp.partial[e] = double(s);
+                } else {
+                    kp.partial[e] = double(s);
+                }
             }
         }
         __syncthreads();
@@ -407,24 +414,36 @@ __device__ void run_reduce_stack(const KParams& kp, int block, int yg, int nrhs)
     const int o = yg * out + ol;
     const bool f64 = bd.fmt == F64 || sizeof(AT) == 8;
     if (o < total) {
-        const double* src = kp.partial + bd.s_off * nrhs + o;
         const int n = bd.sleaves;
         double acc_d = 0.0;
         AT acc_a = AT(0);
         int l = s;
-        for (; l + 7 * sl < n; l += 8 * sl) {
-            double v[8];
+        if (kp.part_f32) {                              // fp32 partials: fp32 sums (never f64 here)
+            const float* src = reinterpret_cast<const float*>(kp.partial) + bd.s_off * nrhs + o;
+            for (; l + 7 * sl < n; l += 8 * sl) {
+                float v[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = src[int64_t(l + q * sl) * total];
+                for (int q = 0; q < 8; ++q) v[q] = src[int64_t(l + q * sl) * total];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                if (f64) acc_d += v[q];
-                else acc_a += AT(v[q]);
+                for (int q = 0; q < 8; ++q) acc_a += AT(v[q]);
             }
-        }
-        for (; l < n; l += sl) {
-            if (f64) acc_d += src[int64_t(l) * total];
-            else acc_a += AT(src[int64_t(l) * total]);
+            for (; l < n; l += sl) acc_a += AT(src[int64_t(l) * total]);
+        } else {
+            const double* src = kp.partial + bd.s_off * nrhs + o;
+            for (; l + 7 * sl < n; l += 8 * sl) {
+                double v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = src[int64_t(l + q * sl) * total];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (f64) acc_d += v[q];
+                    else acc_a += AT(v[q]);
+                }
+            }
+            for (; l < n; l += sl) {
+                if (f64) acc_d += src[int64_t(l) * total];
+                else acc_a += AT(src[int64_t(l) * total]);
+            }
         }
         sred[threadIdx.x] = f64 ? acc_d : double(acc_a);
     }
