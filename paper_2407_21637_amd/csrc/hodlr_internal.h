@@ -266,7 +266,8 @@ struct WorkItem {              // (operator, leaf / item / block / tile, right-h
 struct BatchGroup {
     int32_t xy_double, acc_double, wide, rg, ntc;
     int32_t stage_cap, jc;
-    int32_t stacked;           // matrix cores: contraction by stacked tiles (every operator of the group)
+    int32_t stacked;           // matrix cores: contraction by stacked tiles (every operator of the group),
+                               // the most tiles of a unit over the group; 0: by items
     int32_t pad_;
     int64_t lds_contract, lds_expand;
     const BatchOp* ops;        // device

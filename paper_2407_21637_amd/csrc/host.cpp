@@ -1487,8 +1487,9 @@ hodlr_status build_plan(const hodlr_op* ops, int count, const void* const* X, co
             g.rg = ol.rg;
             g.ntc = ol.ntc;
             g.jc = 0;
-            g.stacked = key[4];
+            g.stacked = 0;
         }
+        if (key[4]) g.stacked = std::max(g.stacked, kp.stacked);   // the most tiles of a unit in the group
         g.stage_cap = std::max(g.stage_cap, ol.stage_cap);
         g.lds_contract = std::max(g.lds_contract, ol.lds_contract);
         g.lds_expand = std::max(g.lds_expand, ol.lds_expand);

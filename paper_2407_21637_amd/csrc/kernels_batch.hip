@@ -121,8 +121,11 @@ hipError_t batch_wide(const BatchGroup& g, hipStream_t s) {
     if (g.n_padx)
         hipLaunchKernelGGL((kb_padx<XT>), dim3(g.grid[0]), dim3(256), 0, s, g.ops, g.padx, g.n_padx);
     if (g.n_contract) {
-        if (g.stacked)
+        if (g.stacked > 2)
             hipLaunchKernelGGL((kb_contract_w<XT, AT, NTC, 4>), dim3(g.grid[1]), dim3(kThreads),
+                               size_t(g.lds_contract), s, g.ops, g.contract, g.n_contract);
+        else if (g.stacked)
+            hipLaunchKernelGGL((kb_contract_w<XT, AT, NTC, 2>), dim3(g.grid[1]), dim3(kThreads),
                                size_t(g.lds_contract), s, g.ops, g.contract, g.n_contract);
         else
             hipLaunchKernelGGL((kb_contract_w<XT, AT, NTC, 0>), dim3(g.grid[1]), dim3(kThreads),
