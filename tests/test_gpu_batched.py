@@ -6,7 +6,9 @@ launches.  Each Y_i is compared with the oracle's product of the same stored
 operator under the componentwise tolerance, and with the single-operator
 call on the same inputs (bit for bit: the batched kernels run the same
 device code on the same data).  Repeated calls (graph replay), a capture
-inside a caller's graph, and a batch whose handle set changes are covered.
+inside a caller's graph, and a batch whose handle set changes are covered;
+so are groups of leaf-stacked operators whose units all hold at most two
+tiles (the batch's 2-tile contraction kernel) or mix one and four.
 """
 import sys
 
@@ -15,7 +17,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from tests.parity_util import check  # noqa: E402
+from tests.parity_util import RandomCase, check  # noqa: E402
 from hodlr_inputs import batch as BT  # noqa: E402
 from hodlr_inputs.compress import compress  # noqa: E402
 from oracle import assign as AS  # noqa: E402
@@ -161,3 +163,42 @@ def test_tuned_and_untuned_launches_agree(batch, tmp_path, monkeypatch):
         for line in cache.read_text().splitlines():
             key, o, m = line.split()
             assert "|x" in key and o in ("0", "1") and m in ("1", "2", "4", "8")
+
+
+# (format, ranks per level, accumulation flag, X dtype, nrhs): operators whose
+# every leaf is one stacked unit; "two" has no unit above 2 tiles in any
+# group, "mixed" puts 1- and 4-tile units in one group
+STACKED_BATCHES = {
+    "two": [("e5m2", [5, 4, 4, 3], H.ACC_FP32, "fp32", 8), ("e4m3", [4, 4, 4, 4], H.ACC_FP32, "fp32", 40),
+            ("fp32", [8, 8, 8, 8], H.ACC_FP64, "fp32", 16), ("fp64", [8, 8, 8, 8], H.ACC_FP32, "fp64", 16)],
+    "mixed": [("e4m3", [16, 16, 16, 16], H.ACC_FP32, "fp32", 40), ("e5m2", [5, 4, 4, 3], H.ACC_FP32, "fp32", 40),
+              ("bf16", [12, 12, 12, 12], H.ACC_FP32, "fp32", 24)],
+}
+
+
+@pytest.mark.parametrize("which", sorted(STACKED_BATCHES))
+def test_batched_leaf_stacked_groups(which):
+    rng = np.random.default_rng(21)
+    items = []
+    for i, (fmt, ranks, flags, xy, nrhs) in enumerate(STACKED_BATCHES[which]):
+        case = RandomCase(3000, 4, ranks, seed=30 + i)
+        h = case.library_op()
+        h.set_level_precisions([fmt] * 4, flags)
+        assert h.query()["leaf_stacked"]
+        X = rng.standard_normal((case.n, nrhs))
+        if xy == "fp32":
+            X = X.astype(np.float32).astype(np.float64)
+        dt = torch.float64 if xy == "fp64" else torch.float32
+        Xd = H.colmajor_empty(case.n, nrhs, dt, DEV)
+        Xd.copy_(torch.from_numpy(np.asfortranarray(X)).to(dt))
+        items.append((case, h, fmt, xy, X, Xd, H.colmajor_empty(case.n, nrhs, dt, DEV)))
+    _say(f"[batched] stacked groups '{which}': {[(it[2], it[4].shape[1]) for it in items]}")
+    H.matvec_batched([it[1] for it in items], [it[5] for it in items], [it[6] for it in items])
+    torch.cuda.synchronize()
+    for k, (case, h, fmt, xy, X, Xd, Y) in enumerate(items):
+        y, z, _, _ = case.oracle_product([fmt] * 4, X)
+        st = check(Y.cpu().double().numpy(), y, z, case.chain(), h.info()["acc_dtype"], xy, f"stacked[{k}]")
+        single = h.matvec(Xd)
+        torch.cuda.synchronize()
+        assert torch.equal(single, Y), k
+        _say(f"    [{k}] {fmt} nrhs={X.shape[1]} {xy} ok {st['max_err_over_tau_prob']:.2e}")
