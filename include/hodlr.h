@@ -352,7 +352,14 @@ hodlr_status hodlr_matvec_noalloc(hodlr_op op, const void* X, int64_t ldx, void*
  * stream that is being captured the launches are recorded into the
  * caller's graph instead; that needs a plan made by an earlier call outside
  * capture (E_STATE otherwise), since nothing may be allocated during a
- * capture.  Argument errors are reported before anything is enqueued. */
+ * capture.  Operators with HODLR_BF16 or HODLR_FP16 X/Y (the low working
+ * precision of hodlr_matvec) are not part of the plan: their products run
+ * one after another, after the planned launches, through the
+ * single-operator launches on `stream`, with the same results as
+ * hodlr_matvec; their operands in W are checked and built (once per
+ * precision assignment) before any product is enqueued, and a capture finds
+ * them only when an earlier call outside it built them (E_STATE otherwise).
+ * Argument errors are reported before anything is enqueued. */
 hodlr_status hodlr_matvec_batched(const hodlr_op* ops, int32_t count, const void* const* X,
                                   const int64_t* ldx, void* const* Y, const int64_t* ldy,
                                   const int32_t* nrhs, const int32_t* xy_dtype, hipStream_t stream);

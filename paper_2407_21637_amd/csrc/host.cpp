@@ -1971,8 +1971,10 @@ hodlr_status hodlr_matvec_batched(const hodlr_op* ops, int32_t count, const void
         if (op->device < 0) return fail(HODLR_E_STATE, "ops[%d] is a host-only handle", i);
         if (op->device != ops[0]->device) return fail(HODLR_E_STATE, "operators on different devices");
         if (nrhs[i] < 1) return fail(HODLR_E_ARG, "nrhs[%d] must be >= 1", i);
-        if (xy_dtype[i] != HODLR_FP32 && xy_dtype[i] != HODLR_FP64)
-            return fail(HODLR_E_UNSUPPORTED, "xy_dtype[%d] must be HODLR_FP32 or HODLR_FP64", i);
+        if (xy_dtype[i] != HODLR_FP32 && xy_dtype[i] != HODLR_FP64 && xy_dtype[i] != HODLR_BF16 &&
+            xy_dtype[i] != HODLR_FP16)
+            return fail(HODLR_E_UNSUPPORTED, "xy_dtype[%d] must be HODLR_FP64, HODLR_FP32, HODLR_BF16 or HODLR_FP16",
+                        i);
         if (!X[i] || !Y[i]) return fail(HODLR_E_ARG, "X[%d] or Y[%d] is NULL", i, i);
         if (ldx[i] < op->n || ldy[i] < op->n) return fail(HODLR_E_ARG, "ldx[%d] and ldy[%d] must be >= n", i, i);
     }
@@ -1984,7 +1986,45 @@ hodlr_status hodlr_matvec_batched(const hodlr_op* ops, int32_t count, const void
     }
     hipError_t e = hipSetDevice(ops[0]->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    return batch_run(ops, count, X, ldx, Y, ldy, nrhs, xy_dtype, stream);
+    // products in a low working precision (bf16 / fp16) run one after another
+    // through the single-operator launches; the others as the planned batch
+    std::vector<int> lp, hp;
+    for (int i = 0; i < count; ++i)
+        (xy_dtype[i] == HODLR_BF16 || xy_dtype[i] == HODLR_FP16 ? lp : hp).push_back(i);
+    hodlr_status r;
+    // the low-precision operands (range checks, one build per assignment)
+    // are settled before any product is enqueued
+    for (int i : lp) {
+        KParams kp{};
+        if ((r = prepare_workspace(ops[i], stream, nrhs[i], 2, &kp)) != HODLR_OK) return r;
+        if ((r = ensure_aug(ops[i], xy_dtype[i], kp, stream)) != HODLR_OK) return r;
+    }
+    if (hp.size() == size_t(count)) return batch_run(ops, count, X, ldx, Y, ldy, nrhs, xy_dtype, stream);
+    if (!hp.empty()) {
+        const size_t m = hp.size();
+        std::vector<hodlr_op> o(m);
+        std::vector<const void*> x(m);
+        std::vector<void*> y(m);
+        std::vector<int64_t> lx(m), ly(m);
+        std::vector<int32_t> nr(m), dt(m);
+        for (size_t q = 0; q < m; ++q) {
+            const int i = hp[q];
+            o[q] = ops[i];
+            x[q] = X[i];
+            y[q] = Y[i];
+            lx[q] = ldx[i];
+            ly[q] = ldy[i];
+            nr[q] = nrhs[i];
+            dt[q] = xy_dtype[i];
+        }
+        if ((r = batch_run(o.data(), int(m), x.data(), lx.data(), y.data(), ly.data(), nr.data(), dt.data(),
+                           stream)) != HODLR_OK)
+            return r;
+    }
+    for (int i : lp)
+        if ((r = hodlr_matvec(ops[i], X[i], ldx[i], Y[i], ldy[i], nrhs[i], xy_dtype[i], hstream)) != HODLR_OK)
+            return r;
+    return ok();
 }
 
 hodlr_status hodlr_profile(hodlr_op op, int32_t capacity) {

@@ -202,3 +202,46 @@ def test_batched_leaf_stacked_groups(which):
         torch.cuda.synchronize()
         assert torch.equal(single, Y), k
         _say(f"    [{k}] {fmt} nrhs={X.shape[1]} {xy} ok {st['max_err_over_tau_prob']:.2e}")
+
+
+def test_batched_low_working_precision_with_others():
+    """bf16 and fp16 products in one batched call with fp32 and fp64 ones:
+    each Y equals the single-operator product bit for bit (the same launches
+    run), eagerly and when a caller's graph replays the batch."""
+    rng = np.random.default_rng(41)
+    spec = [("bf16", torch.bfloat16, 3, [6, 5, 4, 4]), ("fp32", torch.float32, 24, [9, 7, 5, 4]),
+            ("fp16", torch.float16, 40, [16, 16, 16, 16]), ("fp64", torch.float64, 2, [5, 5, 5, 5]),
+            ("bf16", torch.bfloat16, 64, [20, 20, 20, 20])]
+    hs, Xs, Ys = [], [], []
+    for i, (name, dt, nrhs, ranks) in enumerate(spec):
+        case = RandomCase(2500 + 300 * i, 4, ranks, seed=50 + i)
+        h = case.library_op()
+        h.set_level_precisions(["e4m3", "bf16", "fp16", "fp32"], H.ACC_FP32)
+        X = H.colmajor_empty(case.n, nrhs, dt, DEV)
+        X.copy_(torch.from_numpy(np.asfortranarray(rng.standard_normal((case.n, nrhs)))).to(dt))
+        hs.append(h)
+        Xs.append(X)
+        Ys.append(H.colmajor_empty(case.n, nrhs, dt, DEV))
+    _say(f"[batched] mixed dtypes {[(s[0], s[2]) for s in spec]}")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        H.matvec_batched(hs, Xs, Ys, stream=s)      # plan and W operands, outside capture
+    s.synchronize()
+    ref = [h.matvec(X) for h, X in zip(hs, Xs)]
+    torch.cuda.synchronize()
+    for k, (y, r) in enumerate(zip(Ys, ref)):
+        assert torch.equal(y, r), k
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        H.matvec_batched(hs, Xs, Ys, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for y in Ys:
+            y.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, (y, r) in enumerate(zip(Ys, ref)):
+            assert torch.equal(y, r), (rep, k)
+    del g
