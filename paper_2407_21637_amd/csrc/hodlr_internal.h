@@ -156,7 +156,7 @@ struct KParams {
     const ETile* etiles;
     const double* tscale;
     const void* aug;             // low working precision: the augmented operands in W (LeafDesc::aug_off)
-    void* Tw;                    // low working precision: T_b in W (sum of round_up(rank, 32) * nrhs)
+    void* Tw;                    // low working precision: T_b in W (sum of round_up(rank, 8) * nrhs)
     double* partial;             // workspace: sum over items of rank * nrhs
     double* T;                   // workspace: sum over blocks of rank * nrhs
     void* xpad;                  // workspace: padded copy of X (npad * nrhs), if needed
